@@ -1,0 +1,163 @@
+/* libls: Lippmann-Schwinger forward model, far field and data-term gradient on MI355X (gfx950).
+ *
+ * Pham, Soubies, Ayoub, Lim, Psaltis, Unser, "Three-Dimensional Optical Diffraction Tomography
+ * with Lippmann-Schwinger Model" (arXiv 1910.13844).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: voxel units, h = 1.  kbh = k_b h with k_b = 2 pi eta_b / lambda0; the contrast passed
+ *   in is f~ = f h^2 = (2 pi h / lambda0)^2 (eta^2 - eta_b^2) (Section "Continuous-Domain
+ *   Formulation").  x_Gamma is given in voxels.
+ * Grid: Omega_n = [[-n/2+1, n/2]]^3 (Theorem 1).  Volume arrays are row-major [z][y][x], x fastest;
+ *   array index i holds the signed position i - n/2 + 1.  Detector arrays are [y][x] (m = n) at the
+ *   same lateral positions.  Batches add a leading illumination index [Q].
+ * Types: complex = interleaved (re, im) in the path's precision: LS_C64 -> float, LS_C128 ->
+ *   double; real arrays (f, gradients) use float / double accordingly.
+ * Memory: every array pointer is DEVICE memory owned by the caller unless marked [host].  The
+ *   library allocates no device memory: device scratch comes from caller-provided workspaces whose
+ *   sizes the *_bytes queries return.  A workspace must not be used by two calls at once.
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work on it and return;
+ *   calls that produce [host] outputs (solve information, loss) synchronise that stream first.
+ * Errors: 0 on success, a negative LS_ERR_* code otherwise; arguments are validated before
+ *   anything is enqueued.  The library never aborts or throws across this interface.  Per-
+ *   illumination non-convergence is not a call failure: it is reported in ls_solve_info.status.
+ */
+#ifndef LS_H_
+#define LS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LS_OK 0
+#define LS_ERR_ARG (-1)       /* invalid argument (sizes, Nyquist condition, null pointers) */
+#define LS_ERR_WORKSPACE (-2) /* workspace or kernel buffer too small */
+#define LS_ERR_UNSUPPORTED (-3) /* grid size / precision combination not built */
+#define LS_ERR_HIP (-4)       /* a HIP runtime call failed; see ls_last_error() */
+
+#define LS_C64 0  /* complex64 fields, FP64 reductions and Krylov scalars */
+#define LS_C128 1 /* complex128 throughout */
+
+/* Geometry of one problem (Theorem 1, Proposition 2, Section on G~). */
+typedef struct {
+  int32_t n;    /* voxels per side; supported: 8, 16, 32, 64, 96, 128 (LS_C64), up to 96 (LS_C128) */
+  int32_t p;    /* Theorem 1 padding factor, even, >= 2 (p = 4 recommended); only the 2n grid is stored */
+  double kbh;   /* k_b h; must satisfy 0 < kbh < pi (Nyquist condition of Theorem 1) */
+  double xg;    /* detector plane position x_Gamma / h; must exceed n/2 (plane outside Omega) */
+  int32_t prec; /* LS_C64 or LS_C128 */
+  int32_t reserved;
+} ls_geom;
+
+typedef struct {
+  double tol;           /* stop when ||b - A x|| / ||b|| <= tol (recursive residual, re-checked in FP64) */
+  int32_t maxit;        /* iteration cap per illumination */
+  int32_t max_restarts; /* restarts allowed after breakdown or a failed true-residual check */
+} ls_solve_opts;
+
+typedef struct {
+  int32_t status;      /* 0 converged, 1 iteration cap, 2 breakdown not recovered, 3 non-finite */
+  int32_t iters;       /* BiCGSTAB iterations */
+  int32_t matvecs;     /* applications of A = I - G diag f */
+  int32_t restarts;
+  double relres_rec;   /* last recursive relative residual */
+  double relres_true;  /* ||b - A x|| / ||b|| recomputed from x (FP64 accumulation) */
+} ls_solve_info;
+
+typedef struct ls_ctx ls_ctx;     /* immutable after ls_green_init; host-side object */
+typedef struct ls_batch ls_batch; /* slot pool for continuous batching; host-side object */
+
+/* Human-readable text for an error code; ls_last_error() gives the last HIP error text. */
+const char* ls_strerror(int code);
+const char* ls_last_error(void);
+
+/* Sizes of the caller-allocated buffers of ls_green_init.  kernel: Fourier-domain volume kernel
+ * and far-field slice kernels plus twiddles (kept for the lifetime of the context); init
+ * workspace: FP64 scratch needed only during ls_green_init. */
+int ls_kernel_bytes(const ls_geom* g, size_t* bytes);
+int ls_init_workspace_bytes(const ls_geom* g, size_t* bytes);
+
+/* Builds the Fourier-domain Green kernels for geometry g (Proposition 2; Section on G~).
+ *   ghat_m = F_{2n}(gm),  gm[k] = (8/p^3) sum_{s in [[0,p/2-1]]^3} F^{-1}_{2n}(ghat_t[(p/2).-s])[k]
+ *            e^{-2 i pi k.s/(np)},  ghat_t the transform of the Green function truncated at
+ *            sqrt(3) L (eqs. (GreenL), (GreenL2));
+ *   far-field slice kernels: 2n-padded 2D DFTs of g(., x_Gamma - z_k) sampled on the voxel grid.
+ * All in FP64, rounded once to the path precision.  kbuf (>= ls_kernel_bytes) must stay valid
+ * while the context is used; ws (>= ls_init_workspace_bytes) may be reused after return.
+ * Synchronises `stream`.  *out receives a host-side context (free with ls_ctx_destroy). */
+int ls_green_init(const ls_geom* g, void* kbuf, size_t kbuf_bytes, void* ws, size_t ws_bytes, void* stream,
+                  ls_ctx** out);
+void ls_ctx_destroy(ls_ctx* ctx);
+
+#define LS_OP_FORWARD 0  /* ls_forward */
+#define LS_OP_FARFIELD 1 /* ls_farfield, ls_farfield_adj */
+#define LS_OP_GRAD 2     /* ls_grad, ls_vjp */
+#define LS_OP_APPLY 3    /* ls_apply_G, ls_apply_A */
+/* Workspace needed to process Q illuminations of operation `op` in one group.  Calls accept any
+ * workspace that fits at least one illumination and process the batch in groups. */
+int ls_workspace_bytes(const ls_ctx* ctx, int32_t Q, int32_t op, size_t* bytes);
+
+/* out_q = G v_q for Q volumes v [Q][N] (Theorem 1 / Proposition 2). */
+int ls_apply_G(const ls_ctx* ctx, const void* v, void* out, int32_t Q, void* ws, size_t ws_bytes, void* stream);
+/* out_q = v_q - G (f . v_q): the operator of eq. (lipp1). */
+int ls_apply_A(const ls_ctx* ctx, const void* f, const void* v, void* out, int32_t Q, void* ws, size_t ws_bytes,
+               void* stream);
+
+/* Forward solve, eq. (lipp1): u_q = (I - G diag f)^{-1} u_in,q for plane waves
+ * u_in,q(x) = exp(i kbh d_q . x), d_q = dirs[3q..3q+2] [host] (unit vectors, (x, y, z) order).
+ * BiCGSTAB (van der Vorst) with x0 = u_in, FP64 inner products and scalars.  u: out [Q][N].
+ * info: [host] Q entries (may be NULL).  Synchronises `stream`. */
+int ls_forward(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, void* u, const ls_solve_opts* opts,
+               ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Far field, eq. (lipp2) with P = I: y_q = G~ (f . u_q) on the detector plane x3 = x_Gamma,
+ * a sum over z-slices of 2D aperiodic convolutions with g.  u: [Q][N]; y: out [Q][m][m]. */
+int ls_farfield(const ls_ctx* ctx, const void* f, const void* u, int32_t Q, void* y, void* ws, size_t ws_bytes,
+                void* stream);
+/* Transpose of G~ (no conjugation unless conj != 0, then applied to conj(r)): out = G~^T r,
+ * r: [Q][m][m], out: [Q][N]. */
+int ls_farfield_adj(const ls_ctx* ctx, const void* r, int32_t conj, int32_t Q, void* out, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Vector-Jacobian product of y_q(f) = G~ diag(f) u_q(f) (Algorithm 1, gradient step):
+ *   grad = sum_q Re(J_q^* gy_q),  gy = dL/dRe(y) + i dL/dIm(y)  [Q][m][m],
+ * evaluated as Re(u_q . w_q) with (I - G diag f) w_q = G~^T conj(gy_q) (one more solve per view).
+ * u: the forward fields [Q][N].  grad: out [N] real.  info: [host] Q entries (adjoint solves). */
+int ls_vjp(const ls_ctx* ctx, const void* f, const void* u, int32_t Q, const void* gy, void* grad,
+           const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Data term of eq. (prob) and its gradient (Algorithm 1, gradient step):
+ *   loss = sum_q ||H_q(f) - y_meas,q||^2 / (2 ||y_meas,q||^2),
+ *   grad = sum_q Re(J_q^* (H_q(f) - y_meas,q)) / ||y_meas,q||^2.
+ * y_meas: [Q][m][m]; grad: out [N]; loss: [host]; info: [host] 2Q entries (forward, then adjoint). */
+int ls_grad(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, const void* y_meas, void* grad,
+            double* loss, const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Continuous batching (slot pool).  A batch holds `nslots` independent solves of eq. (lipp1) on
+ * one context (one grid size); each slot has its own potential, right-hand side and output.
+ * Slots are admitted and harvested between steps while the others keep iterating, so requests
+ * that arrive while others run share the same kernel launches.
+ *   ls_batch_bytes:   workspace for nslots slots.
+ *   ls_batch_create:  host object over the caller's workspace; all slots idle.
+ *   ls_batch_admit:   start a solve in an idle slot: f [N], either dir [host, 3] (plane wave) or
+ *                     b [N] (stored right-hand side, device), and the output x [N] (device).
+ *   ls_batch_step:    run up to `iters` iterations of every running slot (and pending true-
+ *                     residual checks), then synchronise and refresh the slot states.
+ *   ls_batch_poll:    [host] state per slot (0 idle, 1 running, 2 done) and solve info.
+ *   ls_batch_release: mark a done slot idle again. */
+int ls_batch_bytes(const ls_ctx* ctx, int32_t nslots, size_t* bytes);
+int ls_batch_create(const ls_ctx* ctx, int32_t nslots, void* ws, size_t ws_bytes, const ls_solve_opts* opts,
+                    ls_batch** out);
+int ls_batch_admit(ls_batch* b, int32_t slot, const void* f, const double* dir, const void* rhs, void* x,
+                   void* stream);
+int ls_batch_step(ls_batch* b, int32_t iters, void* stream);
+int ls_batch_poll(const ls_batch* b, int32_t* state, ls_solve_info* info);
+int ls_batch_release(ls_batch* b, int32_t slot);
+void ls_batch_destroy(ls_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LS_H_ */

@@ -1,0 +1,234 @@
+"""Python binding of libls with the same names as the C ABI.
+
+PyTorch supplies device memory and HIP streams; every step of the computation runs in the HIP
+kernels behind include/ls.h.  Volumes are [Q, n, n, n] (z, y, x), detector fields [Q, n, n].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """Green kernels of one geometry, resident on the device (ls_green_init)."""
+
+    def __init__(self, n: int, kbh: float, p: int = 4, xg: Optional[float] = None, prec: str = "c64",
+                 device: str = "cuda:0", stream=None):
+        self.lib = L.load()
+        self.n, self.p, self.kbh = int(n), int(p), float(kbh)
+        self.xg = float(n) if xg is None else float(xg)
+        self.prec = prec
+        self.device = torch.device(device)
+        self.cdtype = torch.complex64 if prec == "c64" else torch.complex128
+        self.rdtype = torch.float32 if prec == "c64" else torch.float64
+        self.geom = L.Geom(self.n, self.p, self.kbh, self.xg, L.LS_C64 if prec == "c64" else L.LS_C128, 0)
+        kb, wb = C.c_size_t(), C.c_size_t()
+        L.check(self.lib.ls_kernel_bytes(C.byref(self.geom), C.byref(kb)), "ls_kernel_bytes")
+        L.check(self.lib.ls_init_workspace_bytes(C.byref(self.geom), C.byref(wb)), "ls_init_workspace_bytes")
+        self.kbuf = torch.empty(kb.value, dtype=torch.uint8, device=self.device)
+        ws = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        L.check(self.lib.ls_green_init(C.byref(self.geom), _ptr(self.kbuf), kb.value, _ptr(ws), wb.value,
+                                       _stream(stream), C.byref(h)), "ls_green_init")
+        del ws
+        self.h = h
+        self._ws = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and self.h.value:
+                self.lib.ls_ctx_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def N(self) -> int:
+        return self.n ** 3
+
+    # -- workspaces ------------------------------------------------------------------------
+    def workspace_bytes(self, Q: int, op: int) -> int:
+        b = C.c_size_t()
+        L.check(self.lib.ls_workspace_bytes(self.h, int(Q), int(op), C.byref(b)), "ls_workspace_bytes")
+        return b.value
+
+    def workspace(self, Q: int, op: int, max_bytes: Optional[int] = None) -> torch.Tensor:
+        need = self.workspace_bytes(Q, op)
+        if max_bytes is not None:
+            need = min(need, max_bytes)
+        key = (op,)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            self._ws.pop(key, None)
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def _chk_vol(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        if t.device != self.device or t.dtype != self.cdtype or not t.is_contiguous() or t.shape[-3:] != (self.n,) * 3:
+            raise ValueError(f"{name}: expected contiguous {self.cdtype} [..., {self.n}, {self.n}, {self.n}] on {self.device}")
+        return t
+
+    def _chk_f(self, f: torch.Tensor) -> torch.Tensor:
+        if f.device != self.device or f.dtype != self.rdtype or not f.is_contiguous() or tuple(f.shape) != (self.n,) * 3:
+            raise ValueError(f"f: expected contiguous {self.rdtype} [{self.n}]^3 on {self.device}")
+        return f
+
+    @staticmethod
+    def _opts(tol: float, maxit: int, max_restarts: int) -> L.SolveOpts:
+        return L.SolveOpts(float(tol), int(maxit), int(max_restarts))
+
+    # -- operators -------------------------------------------------------------------------
+    def ls_apply_G(self, v: torch.Tensor, stream=None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+        v = self._chk_vol(v, "v")
+        Q = v.numel() // self.N
+        out = torch.empty_like(v)
+        ws = self.workspace(Q, L.LS_OP_APPLY) if ws is None else ws
+        L.check(self.lib.ls_apply_G(self.h, _ptr(v), _ptr(out), Q, _ptr(ws), ws.numel(), _stream(stream)), "ls_apply_G")
+        return out
+
+    def ls_apply_A(self, f: torch.Tensor, v: torch.Tensor, stream=None) -> torch.Tensor:
+        v = self._chk_vol(v, "v")
+        f = self._chk_f(f)
+        Q = v.numel() // self.N
+        out = torch.empty_like(v)
+        ws = self.workspace(Q, L.LS_OP_APPLY)
+        L.check(self.lib.ls_apply_A(self.h, _ptr(f), _ptr(v), _ptr(out), Q, _ptr(ws), ws.numel(), _stream(stream)),
+                "ls_apply_A")
+        return out
+
+    def ls_forward(self, f: torch.Tensor, dirs, tol: float = 1e-5, maxit: int = 500, max_restarts: int = 3,
+                   u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None
+                   ) -> Tuple[torch.Tensor, List[dict]]:
+        f = self._chk_f(f)
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        Q = d.shape[0]
+        if u is None:
+            u = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device)
+        self._chk_vol(u, "u")
+        ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
+        info = (L.SolveInfo * Q)()
+        o = self._opts(tol, maxit, max_restarts)
+        L.check(self.lib.ls_forward(self.h, _ptr(f), Q, d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(u),
+                                    C.byref(o), info, _ptr(ws), ws.numel(), _stream(stream)), "ls_forward")
+        return u, [i.as_dict() for i in info]
+
+    def ls_farfield(self, f: torch.Tensor, u: torch.Tensor, ws: Optional[torch.Tensor] = None, stream=None
+                    ) -> torch.Tensor:
+        f = self._chk_f(f)
+        u = self._chk_vol(u, "u")
+        Q = u.numel() // self.N
+        y = torch.empty((Q, self.n, self.n), dtype=self.cdtype, device=self.device)
+        ws = self.workspace(Q, L.LS_OP_FARFIELD) if ws is None else ws
+        L.check(self.lib.ls_farfield(self.h, _ptr(f), _ptr(u), Q, _ptr(y), _ptr(ws), ws.numel(), _stream(stream)),
+                "ls_farfield")
+        return y
+
+    def ls_farfield_adj(self, r: torch.Tensor, conj: bool = False, stream=None) -> torch.Tensor:
+        r = r.contiguous()
+        if r.dtype != self.cdtype or r.shape[-2:] != (self.n, self.n):
+            raise ValueError("r: expected [Q, n, n] in the field precision")
+        Q = r.numel() // (self.n * self.n)
+        out = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device)
+        ws = self.workspace(Q, L.LS_OP_FARFIELD)
+        L.check(self.lib.ls_farfield_adj(self.h, _ptr(r), int(bool(conj)), Q, _ptr(out), _ptr(ws), ws.numel(),
+                                         _stream(stream)), "ls_farfield_adj")
+        return out
+
+    def ls_vjp(self, f: torch.Tensor, u: torch.Tensor, gy: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
+               max_restarts: int = 3, ws: Optional[torch.Tensor] = None, stream=None
+               ) -> Tuple[torch.Tensor, List[dict]]:
+        f = self._chk_f(f)
+        u = self._chk_vol(u, "u")
+        gy = gy.contiguous()
+        Q = u.numel() // self.N
+        grad = torch.empty((self.n,) * 3, dtype=self.rdtype, device=self.device)
+        ws = self.workspace(Q, L.LS_OP_GRAD) if ws is None else ws
+        info = (L.SolveInfo * Q)()
+        o = self._opts(tol, maxit, max_restarts)
+        L.check(self.lib.ls_vjp(self.h, _ptr(f), _ptr(u), Q, _ptr(gy), _ptr(grad), C.byref(o), info, _ptr(ws),
+                                ws.numel(), _stream(stream)), "ls_vjp")
+        return grad, [i.as_dict() for i in info]
+
+    def ls_grad(self, f: torch.Tensor, dirs, y_meas: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
+                max_restarts: int = 3, ws: Optional[torch.Tensor] = None, stream=None
+                ) -> Tuple[float, torch.Tensor, List[dict]]:
+        f = self._chk_f(f)
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        Q = d.shape[0]
+        y_meas = y_meas.contiguous()
+        grad = torch.empty((self.n,) * 3, dtype=self.rdtype, device=self.device)
+        ws = self.workspace(Q, L.LS_OP_GRAD) if ws is None else ws
+        info = (L.SolveInfo * (2 * Q))()
+        loss = C.c_double()
+        o = self._opts(tol, maxit, max_restarts)
+        L.check(self.lib.ls_grad(self.h, _ptr(f), Q, d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(y_meas),
+                                 _ptr(grad), C.byref(loss), C.byref(o), info, _ptr(ws), ws.numel(),
+                                 _stream(stream)), "ls_grad")
+        return loss.value, grad, [i.as_dict() for i in info]
+
+
+class Batch:
+    """Slot pool for continuous batching (ls_batch_*)."""
+
+    def __init__(self, ctx: Context, nslots: int, tol: float = 1e-5, maxit: int = 500, max_restarts: int = 3):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.nslots = int(nslots)
+        b = C.c_size_t()
+        L.check(self.lib.ls_batch_bytes(ctx.h, self.nslots, C.byref(b)), "ls_batch_bytes")
+        self.ws = torch.empty(b.value, dtype=torch.uint8, device=ctx.device)
+        o = L.SolveOpts(float(tol), int(maxit), int(max_restarts))
+        h = C.c_void_p()
+        L.check(self.lib.ls_batch_create(ctx.h, self.nslots, _ptr(self.ws), self.ws.numel(), C.byref(o), C.byref(h)),
+                "ls_batch_create")
+        self.h = h
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and self.h.value:
+                self.lib.ls_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def ls_batch_admit(self, slot: int, f: torch.Tensor, x: torch.Tensor, direction=None,
+                       rhs: Optional[torch.Tensor] = None, stream=None) -> None:
+        dptr = None
+        if direction is not None:
+            d = np.ascontiguousarray(np.asarray(direction, dtype=np.float64).reshape(3))
+            self._keep[("dir", slot)] = d
+            dptr = d.ctypes.data_as(C.POINTER(C.c_double))
+        self._keep[slot] = (f, x, rhs)
+        L.check(self.lib.ls_batch_admit(self.h, int(slot), _ptr(f), dptr, _ptr(rhs), _ptr(x), _stream(stream)),
+                "ls_batch_admit")
+
+    def ls_batch_step(self, iters: int, stream=None) -> None:
+        L.check(self.lib.ls_batch_step(self.h, int(iters), _stream(stream)), "ls_batch_step")
+
+    def ls_batch_poll(self):
+        st = (C.c_int32 * self.nslots)()
+        info = (L.SolveInfo * self.nslots)()
+        L.check(self.lib.ls_batch_poll(self.h, st, info), "ls_batch_poll")
+        return list(st), [i.as_dict() for i in info]
+
+    def ls_batch_release(self, slot: int) -> None:
+        L.check(self.lib.ls_batch_release(self.h, int(slot)), "ls_batch_release")
+        self._keep.pop(slot, None)
+        self._keep.pop(("dir", slot), None)

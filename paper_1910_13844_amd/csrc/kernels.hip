@@ -1,0 +1,826 @@
+// Hot-path kernels of the Lippmann-Schwinger forward model on gfx950.
+//
+// The volume operator G of Proposition 2 is a linear convolution of an n^3 field with the
+// modified kernel gm on the 2n grid, i.e. (G v) = crop(F^{-1}_{2n}(ghat_m . F_{2n}(pad v))).
+// Splitting every 2n-point axis transform into its even and odd output frequencies turns the
+// zero-padded 2n-point DFT into two n-point DFTs (the odd one of the input modulated by
+// exp(-i pi j / n)), and the cropped inverse into the sum of two n-point inverse DFTs.  The
+// convolution is evaluated in three passes over HBM:
+//
+//   k_xfwd  [z][y][x] field -> x-spectrum [kx (2n)][z][y]           (prologue fuses f . x and
+//                                                                      the Krylov vector updates)
+//   k_yz    per (slot, kx) plane: y-DFT, z-convolution with ghat_m, inverse y-DFT, all in LDS
+//   k_xinv  [kx][z][y] -> cropped inverse x-DFT -> [z][y][x]          (epilogue fuses x - G(...)
+//                                                                      and FP64 partial dots)
+//
+// The far field (eq. (lipp2), P = I) reuses k_xfwd/k_xinv with k_ff / k_ffT in between.
+// Kernels of the Fourier-domain Green function carry the 1/(2n)^d normalisation of the inverse
+// transforms, so every FFT here is unnormalised.
+#include "fft.hpp"
+#include "launch.hpp"
+
+#include <type_traits>
+
+namespace ls {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> ld(const void* p, size_t i) { return ((const cplx<T>*)p)[i]; }
+template <typename T>
+__device__ __forceinline__ void stv(void* p, size_t i, cplx<T> v) { ((cplx<T>*)p)[i] = v; }
+
+__device__ __forceinline__ bool slot_active(const PassArgs& a, int slot) {
+  return (a.mask >> a.st[slot].status) & 1u;
+}
+
+// Plane wave exp(i k d.x), x = signed voxel position (index - n/2 + 1).  The phase is formed
+// in FP64 and reduced to [-pi, pi] before a single-precision sincos on the c64 path.
+template <typename T>
+__device__ __forceinline__ cplx<T> plane_wave(const SlotDesc& d, int n, int z, int y, int x) {
+  const double c0 = 1.0 - 0.5 * n;
+  const double ph = d.k * (d.d[0] * (x + c0) + d.d[1] * (y + c0) + d.d[2] * (z + c0));
+  if constexpr (std::is_same<T, double>::value) {
+    double s, c;
+    sincos(ph, &s, &c);
+    return {c, s};
+  } else {
+    const double r = ph - 6.283185307179586477 * rint(ph * 0.15915494309189533577);
+    float s, c;
+    sincosf((float)r, &s, &c);
+    return {c, s};
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> rhs_b(const SlotDesc& d, int n, size_t idx, int z, int y, int x) {
+  if (d.vec[V_B]) return ld<T>(d.vec[V_B], idx);
+  return plane_wave<T>(d, n, z, y, x);
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> scal(const double* v) { return {(T)v[0], (T)v[1]}; }
+
+__device__ __forceinline__ double* part_ptr(const PassArgs& a, int slot, int blk, int j) {
+  return a.part + (((size_t)slot * a.part_stride + blk) * PART_K + j) * 2;
+}
+
+// =============================================================================================
+// k_xfwd: prologue, zero-extension n -> 2n along x and the two n-point x-DFTs of each row.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
+  constexpr int TY = N < 16 ? N : 16;
+  constexpr int NYT = N / TY;
+  constexpr int PITCH = N + 1;
+  constexpr int L = Lanes<N>::value;
+  constexpr int NG = 256 / L;
+  __shared__ cplx<T> bufE[TY * PITCH];
+  __shared__ cplx<T> bufO[TY * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int per = a.nz * NYT;
+  const int slot = blockIdx.x / per;
+  const int blk = blockIdx.x - slot * per;
+  if (!slot_active(a, slot)) return;
+  const int z = blk / NYT;
+  const int y0 = (blk - z * NYT) * TY;
+  const SlotDesc& d = a.desc[slot];
+  const SlotState& st = a.st[slot];
+  for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
+  __syncthreads();
+
+  const size_t row0 = ((size_t)z * N + y0) * N;
+  const T* f = (const T*)d.f;
+  const int mode = a.mode;
+  const cplx<T> alpha = scal<T>(st.alpha), beta = scal<T>(st.beta), omega = scal<T>(st.omega);
+  const bool restart = st.restart_flag != 0;
+  void* vin = d.vec[a.sel];
+  double ss = 0.0;
+  for (int i = tid; i < TY * N; i += 256) {
+    const int yy = i / N;
+    const int x = i - yy * N;
+    const size_t idx = row0 + i;
+    cplx<T> w;
+    if (mode == PRO_F_VEC) {
+      w = f[idx] * ld<T>(vin, idx);
+    } else if (mode == PRO_F_B) {
+      w = f[idx] * rhs_b<T>(d, N, idx, z, y0 + yy, x);
+    } else if (mode == PRO_P) {
+      const cplx<T> r = ld<T>(d.vec[V_R], idx);
+      cplx<T> p;
+      if (restart) {
+        p = r;
+        stv<T>(d.vec[V_RH], idx, r);
+      } else {
+        p = r + beta * (ld<T>(d.vec[V_P], idx) - omega * ld<T>(d.vec[V_V], idx));
+      }
+      stv<T>(d.vec[V_P], idx, p);
+      w = f[idx] * p;
+    } else if (mode == PRO_S) {
+      const cplx<T> s = ld<T>(d.vec[V_R], idx) - alpha * ld<T>(d.vec[V_V], idx);
+      stv<T>(d.vec[V_S], idx, s);
+      ss += (double)s.re * s.re + (double)s.im * s.im;
+      w = f[idx] * s;
+    } else if (mode == PRO_VEC) {
+      w = ld<T>(vin, idx);
+    } else {
+      w = conj(ld<T>(vin, idx));
+    }
+    bufE[yy * PITCH + x] = w;
+    bufO[yy * PITCH + x] = w * tw[x];
+  }
+  __syncthreads();
+  {
+    const int g = tid / L, lane = tid - (tid / L) * L;
+    for (int t = g; t < 2 * TY; t += NG) {
+      cplx<T>* base = t < TY ? bufE + t * PITCH : bufO + (t - TY) * PITCH;
+      fft_group<T, N, -1, 2>(base, 1, lane, tw);
+    }
+  }
+  __syncthreads();
+  cplx<T>* spec = (cplx<T>*)d.vec[a.spec];
+  for (int i = tid; i < 2 * N * TY; i += 256) {
+    const int yy = i % TY;
+    const int kx = i / TY;
+    const cplx<T>* src = (kx & 1) ? bufO : bufE;
+    spec[((size_t)kx * a.nz + z) * N + y0 + yy] = src[yy * PITCH + (kx >> 1)];
+  }
+  if (mode == PRO_S) {
+    double v[1] = {ss};
+    block_sum<1>(v, red);
+    if (tid == 0) {
+      double* pp = part_ptr(a, slot, blk, 0);
+      pp[0] = v[0];
+      pp[1] = 0.0;
+    }
+  }
+}
+
+// =============================================================================================
+// k_xinv: inverse x-DFTs (even + modulated odd half), crop to n, epilogue and FP64 partials.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
+  constexpr int TY = N < 16 ? N : 16;
+  constexpr int NYT = N / TY;
+  constexpr int PITCH = N + 1;
+  constexpr int L = Lanes<N>::value;
+  constexpr int NG = 256 / L;
+  __shared__ cplx<T> bufE[TY * PITCH];
+  __shared__ cplx<T> bufO[TY * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ double red[6 * 4];
+  const int tid = threadIdx.x;
+  const int per = a.nz * NYT;
+  const int slot = blockIdx.x / per;
+  const int blk = blockIdx.x - slot * per;
+  if (!slot_active(a, slot)) return;
+  const int z = blk / NYT;
+  const int y0 = (blk - z * NYT) * TY;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
+  const cplx<T>* spec = (const cplx<T>*)d.vec[a.spec];
+  for (int i = tid; i < 2 * N * TY; i += 256) {
+    const int yy = i % TY;
+    const int kx = i / TY;
+    cplx<T>* dst = (kx & 1) ? bufO : bufE;
+    dst[yy * PITCH + (kx >> 1)] = spec[((size_t)kx * a.nz + z) * N + y0 + yy];
+  }
+  __syncthreads();
+  {
+    const int g = tid / L, lane = tid - (tid / L) * L;
+    for (int t = g; t < 2 * TY; t += NG) {
+      cplx<T>* base = t < TY ? bufE + t * PITCH : bufO + (t - TY) * PITCH;
+      fft_group<T, N, +1, 2>(base, 1, lane, tw);
+    }
+  }
+  __syncthreads();
+  const size_t row0 = ((size_t)z * N + y0) * N;
+  const int mode = a.mode;
+  cplx<double> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
+  for (int i = tid; i < TY * N; i += 256) {
+    const int yy = i / N;
+    const int x = i - yy * N;
+    const size_t idx = row0 + i;
+    const cplx<T> g = bufE[yy * PITCH + x] + mulc(bufO[yy * PITCH + x], tw[x]);
+    if (mode == EPI_STORE) {
+      stv<T>(d.vec[a.sel], idx, g);
+    } else if (mode == EPI_AXV) {
+      const cplx<T> v = ld<T>(d.vec[V_P], idx) - g;
+      stv<T>(d.vec[V_V], idx, v);
+      dot_acc(a0, ld<T>(d.vec[V_RH], idx), v);
+    } else if (mode == EPI_AXT) {
+      const cplx<T> s = ld<T>(d.vec[V_S], idx);
+      const cplx<T> t = s - g;
+      stv<T>(d.vec[V_T], idx, t);
+      dot_acc(a1, t, s);
+      a2.re += (double)t.re * t.re + (double)t.im * t.im;
+    } else if (mode == EPI_R0) {
+      const cplx<T> b = rhs_b<T>(d, N, idx, z, y0 + yy, x);
+      stv<T>(d.vec[V_X], idx, b);
+      stv<T>(d.vec[V_R], idx, g);
+      stv<T>(d.vec[V_RH], idx, g);
+      a0.re += (double)g.re * g.re + (double)g.im * g.im;
+      a1.re += (double)b.re * b.re + (double)b.im * b.im;
+    } else if (mode == EPI_TRUE) {
+      const cplx<T> b = rhs_b<T>(d, N, idx, z, y0 + yy, x);
+      const cplx<T> r = (b - ld<T>(d.vec[V_X], idx)) + g;
+      stv<T>(d.vec[V_R], idx, r);
+      a0.re += (double)r.re * r.re + (double)r.im * r.im;
+    } else {  // EPI_AX
+      stv<T>(d.vec[a.sel2], idx, ld<T>(d.vec[a.sel], idx) - g);
+    }
+  }
+  if (mode == EPI_AXV || mode == EPI_AXT || mode == EPI_R0 || mode == EPI_TRUE) {
+    double v[6] = {a0.re, a0.im, a1.re, a1.im, a2.re, a2.im};
+    block_sum<6>(v, red);
+    if (tid == 0) {
+      if (mode == EPI_AXV || mode == EPI_TRUE) {
+        double* pp = part_ptr(a, slot, blk, 0);
+        pp[0] = v[0];
+        pp[1] = v[1];
+      } else if (mode == EPI_R0) {
+        double* pp = part_ptr(a, slot, blk, 0);
+        pp[0] = v[0];
+        pp[1] = 0.0;
+        pp[2] = v[2];
+        pp[3] = 0.0;
+      } else {  // EPI_AXT: entries 1 and 2 (entry 0 holds ||s||^2 from k_xfwd)
+        double* pp = part_ptr(a, slot, blk, 1);
+        pp[0] = v[2];
+        pp[1] = v[3];
+        pp[2] = v[4];
+        pp[3] = 0.0;
+      }
+    }
+  }
+}
+
+// =============================================================================================
+// Plane kernels: one workgroup per (slot, kx) plane of the x-spectrum, the whole n x n plane in
+// LDS.  Blocks are numbered so that consecutive blocks on one XCD (workgroups go round-robin
+// over the 8 XCDs) share kx and therefore the same kernel plane in that XCD's L2.
+template <int N>
+struct PlaneCfg {
+  static constexpr int NT = N * N >= 16384 ? 1024 : (N * N >= 8192 ? 512 : (N * N >= 256 ? 256 : N * N));
+  static constexpr int PER = N * N / NT;
+  static constexpr int PITCH = N + 1;
+  static_assert(PER * NT == N * N, "plane must split evenly over the block");
+};
+
+__device__ __forceinline__ void plane_decode(const PassArgs& a, int& kx, int& slot) {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  kx = lin / a.nslots;
+  slot = lin - kx * a.nslots;
+}
+
+// z-convolution of one column (length N, stride `pitch` in LDS) with the kernel row
+// krow[kz], kz in [0, 2N): the 2N-point zero-padded DFT is split into its even and odd output
+// frequencies, each multiplied by its kernel samples and inverted, and the two halves recombined.
+template <typename T, int N>
+__device__ __forceinline__ void zconv(cplx<T>* col, int pitch, int lane, const cplx<T>* tw, const cplx<T>* krow) {
+  constexpr int E = Plan<N>::E;
+  constexpr int L = N / E;
+  cplx<T> orig[E], ev[E];
+  wave_sync();
+#pragma unroll
+  for (int e = 0; e < E; ++e) orig[e] = col[(lane + e * L) * pitch];
+  fft_group<T, N, -1, 2>(col, pitch, lane, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int m = lane + e * L;
+    col[m * pitch] = col[m * pitch] * krow[2 * m];
+  }
+  fft_group<T, N, +1, 2>(col, pitch, lane, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int zz = lane + e * L;
+    ev[e] = col[zz * pitch];
+    col[zz * pitch] = orig[e] * tw[zz];
+  }
+  fft_group<T, N, -1, 2>(col, pitch, lane, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int m = lane + e * L;
+    col[m * pitch] = col[m * pitch] * krow[2 * m + 1];
+  }
+  fft_group<T, N, +1, 2>(col, pitch, lane, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int zz = lane + e * L;
+    col[zz * pitch] = ev[e] + mulc(col[zz * pitch], tw[zz]);
+  }
+  wave_sync();
+}
+
+// k_yz: (y, z) part of the volume convolution for one x-frequency plane, in place.
+// Kernel layout: [kx' in 0..n][ky in 0..2n)[kz in 0..2n), kx' = min(kx, 2n - kx).
+template <typename T, int N>
+__global__ __launch_bounds__(PlaneCfg<N>::NT) void k_yz(PassArgs a) {
+  using C = PlaneCfg<N>;
+  constexpr int NT = C::NT, PER = C::PER, PITCH = C::PITCH;
+  constexpr int L = Lanes<N>::value;
+  constexpr int NG = NT / L;
+  __shared__ cplx<T> plane[N * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  int kx, slot;
+  plane_decode(a, kx, slot);
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  cplx<T>* S = (cplx<T>*)d.vec[a.spec] + (size_t)kx * N * N;
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
+  const int g = tid / L, lane = tid - (tid / L) * L;
+  cplx<T> acc[PER];
+  __syncthreads();
+#pragma unroll 1
+  for (int par = 0; par < 2; ++par) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = tid + j * NT;
+      const int zz = i / N, y = i - zz * N;
+      cplx<T> v = S[i];
+      if (par) v = v * tw[y];
+      plane[zz * PITCH + y] = v;
+    }
+    __syncthreads();
+    for (int t = g; t < N; t += NG) fft_group<T, N, -1, 2>(plane + t * PITCH, 1, lane, tw);
+    __syncthreads();
+    for (int c = g; c < N; c += NG) zconv<T, N>(plane + c, PITCH, lane, tw, K + (size_t)(2 * c + par) * (2 * N));
+    __syncthreads();
+    for (int t = g; t < N; t += NG) fft_group<T, N, +1, 2>(plane + t * PITCH, 1, lane, tw);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = tid + j * NT;
+      const int zz = i / N, y = i - zz * N;
+      if (par == 0)
+        acc[j] = plane[zz * PITCH + y];
+      else
+        S[i] = acc[j] + mulc(plane[zz * PITCH + y], tw[y]);
+    }
+    __syncthreads();
+  }
+}
+
+// k_ff: far field, stage 2 of 3.  For one x-frequency plane of the spectrum of f.u:
+// y-DFT of every z-row, multiply by the slice kernels Khat_z(kx, ky), sum over z, cropped
+// inverse y-DFT.  Output [kx][y] (an x-spectrum with nz = 1) in vec[sel].
+// Kernel layout: [kx' in 0..n][z in 0..n)[ky in 0..2n).
+template <typename T, int N>
+__global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ff(PassArgs a) {
+  using C = PlaneCfg<N>;
+  constexpr int NT = C::NT, PER = C::PER, PITCH = C::PITCH;
+  constexpr int L = Lanes<N>::value;
+  constexpr int NG = NT / L;
+  __shared__ cplx<T> plane[N * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> yv[2 * N];
+  int kx, slot;
+  plane_decode(a, kx, slot);
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  const cplx<T>* S = (const cplx<T>*)d.vec[a.spec] + (size_t)kx * N * N;
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (2 * N * N);
+  const int g = tid / L, lane = tid - (tid / L) * L;
+  __syncthreads();
+#pragma unroll 1
+  for (int par = 0; par < 2; ++par) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = tid + j * NT;
+      const int zz = i / N, y = i - zz * N;
+      cplx<T> v = S[i];
+      if (par) v = v * tw[y];
+      plane[zz * PITCH + y] = v;
+    }
+    __syncthreads();
+    for (int t = g; t < N; t += NG) fft_group<T, N, -1, 2>(plane + t * PITCH, 1, lane, tw);
+    __syncthreads();
+    for (int c = tid; c < N; c += NT) {
+      cplx<T> acc = {0, 0};
+      const cplx<T>* kz = K + 2 * c + par;
+      for (int zz = 0; zz < N; ++zz) acc = acc + kz[(size_t)zz * 2 * N] * plane[zz * PITCH + c];
+      yv[par * N + c] = acc;
+    }
+    __syncthreads();
+  }
+  if (g < 2) fft_group<T, N, +1, 2>(yv + g * N, 1, lane, tw);
+  __syncthreads();
+  cplx<T>* out = (cplx<T>*)d.vec[a.sel] + (size_t)kx * N;
+  for (int y = tid; y < N; y += NT) out[y] = yv[y] + mulc(yv[N + y], tw[y]);
+}
+
+// k_ffT: transpose of the far field, stage 2 of 3.  Input: the x-spectrum [kx][y] (nz = 1) of a
+// detector field in vec[sel].  For one kx: y-DFT of the row, multiply by every slice kernel,
+// cropped inverse y-DFT of each z-row.  Output: x-spectrum plane [z][y] of vec[spec].
+template <typename T, int N>
+__global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
+  using C = PlaneCfg<N>;
+  constexpr int NT = C::NT, PER = C::PER, PITCH = C::PITCH;
+  constexpr int L = Lanes<N>::value;
+  constexpr int NG = NT / L;
+  __shared__ cplx<T> plane[N * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> rv[2 * N];
+  int kx, slot;
+  plane_decode(a, kx, slot);
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  __syncthreads();
+  const cplx<T>* row = (const cplx<T>*)d.vec[a.sel] + (size_t)kx * N;
+  for (int y = tid; y < N; y += NT) {
+    const cplx<T> v = row[y];
+    rv[y] = v;
+    rv[N + y] = v * tw[y];
+  }
+  const int g = tid / L, lane = tid - (tid / L) * L;
+  __syncthreads();
+  if (g < 2) fft_group<T, N, -1, 2>(rv + g * N, 1, lane, tw);
+  __syncthreads();
+  cplx<T>* S = (cplx<T>*)d.vec[a.spec] + (size_t)kx * N * N;
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (2 * N * N);
+  cplx<T> acc[PER];
+#pragma unroll 1
+  for (int par = 0; par < 2; ++par) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = tid + j * NT;
+      const int zz = i / N, c = i - zz * N;
+      plane[zz * PITCH + c] = K[(size_t)zz * 2 * N + 2 * c + par] * rv[par * N + c];
+    }
+    __syncthreads();
+    for (int t = g; t < N; t += NG) fft_group<T, N, +1, 2>(plane + t * PITCH, 1, lane, tw);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = tid + j * NT;
+      const int zz = i / N, y = i - zz * N;
+      if (par == 0)
+        acc[j] = plane[zz * PITCH + y];
+      else
+        S[i] = acc[j] + mulc(plane[zz * PITCH + y], tw[y]);
+    }
+    __syncthreads();
+  }
+}
+
+// =============================================================================================
+// BiCGSTAB vector update x += alpha p + omega s, r = s - omega t, with <rh, r> and ||r||^2.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_update(PassArgs a) {
+  constexpr int TY = N < 16 ? N : 16;
+  constexpr int NYT = N / TY;
+  __shared__ double red[4 * 4];
+  const int tid = threadIdx.x;
+  const int per = a.nz * NYT;
+  const int slot = blockIdx.x / per;
+  const int blk = blockIdx.x - slot * per;
+  if (!slot_active(a, slot)) return;
+  const SlotDesc& d = a.desc[slot];
+  const SlotState& st = a.st[slot];
+  const size_t row0 = (size_t)blk * TY * N;
+  const cplx<T> alpha = scal<T>(st.alpha), omega = scal<T>(st.omega);
+  if (st.status == ST_HALF) {
+    for (int i = tid; i < TY * N; i += 256) {
+      const size_t idx = row0 + i;
+      stv<T>(d.vec[V_X], idx, ld<T>(d.vec[V_X], idx) + alpha * ld<T>(d.vec[V_P], idx));
+    }
+    return;
+  }
+  cplx<double> rho = {0, 0};
+  double rr = 0.0;
+  for (int i = tid; i < TY * N; i += 256) {
+    const size_t idx = row0 + i;
+    const cplx<T> s = ld<T>(d.vec[V_S], idx);
+    const cplx<T> t = ld<T>(d.vec[V_T], idx);
+    stv<T>(d.vec[V_X], idx, ld<T>(d.vec[V_X], idx) + alpha * ld<T>(d.vec[V_P], idx) + omega * s);
+    const cplx<T> r = s - omega * t;
+    stv<T>(d.vec[V_R], idx, r);
+    dot_acc(rho, ld<T>(d.vec[V_RH], idx), r);
+    rr += (double)r.re * r.re + (double)r.im * r.im;
+  }
+  double v[3] = {rho.re, rho.im, rr};
+  block_sum<3>(v, red);
+  if (tid == 0) {
+    double* pp = part_ptr(a, slot, blk, 0);
+    pp[0] = v[0];
+    pp[1] = v[1];
+    pp[2] = v[2];
+    pp[3] = 0.0;
+  }
+}
+
+// =============================================================================================
+// Per-slot scalar step of BiCGSTAB.  One block per slot sums the block partials in a fixed
+// order (deterministic), then thread 0 advances the recurrence in FP64 complex arithmetic.
+__device__ __forceinline__ cplx<double> cdiv(cplx<double> a, cplx<double> b) {
+  const double den = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+}
+__device__ __forceinline__ cplx<double> cmul(cplx<double> a, cplx<double> b) { return a * b; }
+__device__ __forceinline__ cplx<double> getc(const double* v) { return {v[0], v[1]}; }
+__device__ __forceinline__ void putc(double* v, cplx<double> c) {
+  v[0] = c.re;
+  v[1] = c.im;
+}
+
+__device__ __forceinline__ void fresh_restart(SlotState& st) {
+  // rh = r (applied by the next p-update), p = v = 0, rho_prev = alpha = omega = 1
+  st.restart_flag = 1;
+  st.nrh = st.rr;
+  st.rho[0] = st.rr * st.rr;
+  st.rho[1] = 0.0;
+  st.rho_prev[0] = st.alpha[0] = st.omega[0] = 1.0;
+  st.rho_prev[1] = st.alpha[1] = st.omega[1] = 0.0;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_scalar(PassArgs a, double eps) {
+  __shared__ double red[6 * 4];
+  const int slot = blockIdx.x;
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < a.part_stride; b += 256) {
+    const double* pp = a.part + ((size_t)slot * a.part_stride + b) * PART_K * 2;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v[j] += pp[j];
+  }
+  block_sum<6>(v, red);
+  if (tid != 0) return;
+  SlotState& st = a.st[slot];
+  const cplx<double> p0 = {v[0], v[1]}, p1 = {v[2], v[3]}, p2 = {v[4], v[5]};
+  if (KIND == SC_INIT) {
+    st.matvecs += 1;
+    st.nb = sqrt(p1.re);
+    st.rr = sqrt(p0.re);
+    if (!(st.nb > 0.0)) {
+      st.relres = st.relres_true = 0.0;
+      st.status = isfinite(st.nb) ? ST_OK : ST_NONFIN;
+      return;
+    }
+    st.relres = st.rr / st.nb;
+    if (!isfinite(st.relres)) {
+      st.status = ST_NONFIN;
+      return;
+    }
+    if (st.relres <= st.tol) {
+      st.relres_true = st.relres;
+      st.status = ST_OK;
+      return;
+    }
+    fresh_restart(st);
+    st.restart_flag = 1;
+    st.beta[0] = st.rho[0];
+    st.beta[1] = 0.0;
+    st.status = ST_RUN;
+  } else if (KIND == SC_ALPHA) {
+    st.matvecs += 1;
+    const cplx<double> rv = p0;
+    const cplx<double> al = cdiv(getc(st.rho), rv);
+    if (!(isfinite(al.re) && isfinite(al.im))) {
+      st.status = (rv.re == 0.0 && rv.im == 0.0) ? ST_BREAK : ST_NONFIN;
+      return;
+    }
+    putc(st.alpha, al);
+    st.restart_flag = 0;
+  } else if (KIND == SC_OMEGA) {
+    st.matvecs += 1;
+    const double ns = sqrt(p0.re);
+    if (ns / st.nb <= st.tol) {
+      st.rr = ns;
+      st.status = ST_HALF;
+      return;
+    }
+    const cplx<double> om = {p1.re / p2.re, p1.im / p2.re};
+    if (!(isfinite(om.re) && isfinite(om.im))) {
+      st.status = ST_NONFIN;
+      return;
+    }
+    putc(st.omega, om);
+  } else if (KIND == SC_BETA) {
+    st.iters += 1;
+    if (st.status == ST_HALF) {
+      st.relres = st.rr / st.nb;
+      st.status = ST_CHECK;
+      return;
+    }
+    st.rho_prev[0] = st.rho[0];
+    st.rho_prev[1] = st.rho[1];
+    st.rr = sqrt(v[2]);
+    st.relres = st.rr / st.nb;
+    if (!isfinite(st.relres)) {
+      st.status = ST_NONFIN;
+      return;
+    }
+    if (st.relres <= st.tol || st.iters >= st.maxit) {
+      st.status = ST_CHECK;
+      return;
+    }
+    cplx<double> rho = p0;
+    const bool om_zero = st.omega[0] == 0.0 && st.omega[1] == 0.0;
+    if (om_zero || sqrt(rho.re * rho.re + rho.im * rho.im) <= eps * st.nrh * st.rr) {
+      st.restarts += 1;
+      fresh_restart(st);
+      rho = getc(st.rho);
+    }
+    const cplx<double> be = cmul(cdiv(rho, getc(st.rho_prev)), cdiv(getc(st.alpha), getc(st.omega)));
+    putc(st.beta, be);
+    putc(st.rho, rho);
+  } else if (KIND == SC_FINAL) {
+    st.matvecs += 1;
+    const double rt = sqrt(p0.re);
+    st.relres_true = rt / st.nb;
+    if (st.relres_true <= st.tol) {
+      st.status = ST_OK;
+    } else if (st.iters >= st.maxit) {
+      st.status = ST_MAXIT;
+    } else if (st.restarts >= st.max_restarts) {
+      st.status = ST_BREAK;
+    } else {
+      st.rr = rt;
+      st.restarts += 1;
+      fresh_restart(st);
+      st.beta[0] = st.rho[0];
+      st.beta[1] = 0.0;
+      st.status = ST_RUN;
+    }
+  }
+}
+
+// =============================================================================================
+// grad[i] (+)= sum_q w_q Re(u_q[i] wbar_q[i]), summed over slots in index order in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_accum(const SlotDesc* desc, const double* w, int nslots, int sel_u,
+                                                    int sel_w, double* grad, size_t N, int accumulate) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double s = accumulate ? grad[i] : 0.0;
+  for (int q = 0; q < nslots; ++q) {
+    const cplx<T> u = ld<T>(desc[q].vec[sel_u], i);
+    const cplx<T> wb = ld<T>(desc[q].vec[sel_w], i);
+    const double wq = w ? 1.0 / w[2 * q + 1] : 1.0;
+    s += wq * ((double)u.re * wb.re - (double)u.im * wb.im);
+  }
+  grad[i] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_convert(const double* src, T* dst, size_t N) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) dst[i] = (T)src[i];
+}
+
+// r = y - ymeas per view and FP64 ||r||^2, ||ymeas||^2 (one block per view, fixed order).
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual(const cplx<T>* y, const cplx<T>* ym, int M, cplx<T>* r,
+                                                  double* stats) {
+  __shared__ double red[2 * 4];
+  const int q = blockIdx.x;
+  double v[2] = {0, 0};
+  for (int i = threadIdx.x; i < M; i += 256) {
+    const size_t idx = (size_t)q * M + i;
+    const cplx<T> a = y[idx], b = ym[idx];
+    const cplx<T> d = a - b;
+    r[idx] = d;
+    v[0] += (double)d.re * d.re + (double)d.im * d.im;
+    v[1] += (double)b.re * b.re + (double)b.im * b.im;
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    stats[2 * q] = v[0];
+    stats[2 * q + 1] = v[1];
+  }
+}
+
+// =============================================================================================
+// launchers
+template <typename T, int N>
+static hipError_t xfwd_t(const PassArgs& a, hipStream_t s) {
+  const int nb = a.nslots * a.nz * (N / (N < 16 ? N : 16));
+  hipLaunchKernelGGL((k_xfwd<T, N>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t xinv_t(const PassArgs& a, hipStream_t s) {
+  const int nb = a.nslots * a.nz * (N / (N < 16 ? N : 16));
+  hipLaunchKernelGGL((k_xinv<T, N>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t update_t(const PassArgs& a, hipStream_t s) {
+  const int nb = a.nslots * a.nz * (N / (N < 16 ? N : 16));
+  hipLaunchKernelGGL((k_update<T, N>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t yz_t(const PassArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_yz<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t ff_t(const PassArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_ff<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_ffT<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+#define LS_DISPATCH_F(FN, n, ...)                         \
+  switch (n) {                                            \
+    case 8: return FN<float, 8>(__VA_ARGS__);             \
+    case 16: return FN<float, 16>(__VA_ARGS__);           \
+    case 32: return FN<float, 32>(__VA_ARGS__);           \
+    case 64: return FN<float, 64>(__VA_ARGS__);           \
+    case 96: return FN<float, 96>(__VA_ARGS__);           \
+    case 128: return FN<float, 128>(__VA_ARGS__);         \
+    default: return hipErrorInvalidValue;                 \
+  }
+#define LS_DISPATCH_D(FN, n, ...)                         \
+  switch (n) {                                            \
+    case 8: return FN<double, 8>(__VA_ARGS__);            \
+    case 16: return FN<double, 16>(__VA_ARGS__);          \
+    case 32: return FN<double, 32>(__VA_ARGS__);          \
+    case 64: return FN<double, 64>(__VA_ARGS__);          \
+    case 96: return FN<double, 96>(__VA_ARGS__);          \
+    default: return hipErrorInvalidValue;                 \
+  }
+#define LS_DISPATCH(FN, dbl, n, ...)   \
+  if (dbl) {                           \
+    LS_DISPATCH_D(FN, n, __VA_ARGS__)  \
+  } else {                             \
+    LS_DISPATCH_F(FN, n, __VA_ARGS__)  \
+  }
+
+bool fused_supported(int n, bool dbl) {
+  if (dbl) return n == 8 || n == 16 || n == 32 || n == 64 || n == 96;
+  return n == 8 || n == 16 || n == 32 || n == 64 || n == 96 || n == 128;
+}
+
+hipError_t launch_xfwd(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(xfwd_t, dbl, n, a, s) }
+hipError_t launch_xinv(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(xinv_t, dbl, n, a, s) }
+hipError_t launch_yz(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(yz_t, dbl, n, a, s) }
+hipError_t launch_ff(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(ff_t, dbl, n, a, s) }
+hipError_t launch_ffT(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(ffT_t, dbl, n, a, s) }
+hipError_t launch_update(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(update_t, dbl, n, a, s) }
+
+hipError_t launch_scalar(int kind, bool dbl, const PassArgs& a, hipStream_t s) {
+  const double eps = dbl ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+  switch (kind) {
+    case SC_INIT: hipLaunchKernelGGL(k_scalar<SC_INIT>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
+    case SC_ALPHA: hipLaunchKernelGGL(k_scalar<SC_ALPHA>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
+    case SC_OMEGA: hipLaunchKernelGGL(k_scalar<SC_OMEGA>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
+    case SC_BETA: hipLaunchKernelGGL(k_scalar<SC_BETA>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
+    case SC_FINAL: hipLaunchKernelGGL(k_scalar<SC_FINAL>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_accum(bool dbl, int n, const SlotDesc* desc, const double* w, int nslots, int sel_u,
+                             int sel_w, void* grad, int accumulate, hipStream_t s) {
+  const size_t N = (size_t)n * n * n;
+  const int nb = (int)((N + 255) / 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_grad_accum<double>, dim3(nb), dim3(256), 0, s, desc, w, nslots, sel_u, sel_w, (double*)grad,
+                       N, accumulate);
+  else
+    hipLaunchKernelGGL(k_grad_accum<float>, dim3(nb), dim3(256), 0, s, desc, w, nslots, sel_u, sel_w, (double*)grad,
+                       N, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(bool dbl, const double* src, void* dst, size_t N, hipStream_t s) {
+  const int nb = (int)((N + 255) / 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_convert<double>, dim3(nb), dim3(256), 0, s, src, (double*)dst, N);
+  else
+    hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(256), 0, s, src, (float*)dst, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(bool dbl, int m, const void* y, const void* ymeas, int Q, void* r, double* stats,
+                           hipStream_t s) {
+  const int M = m * m;
+  if (dbl)
+    hipLaunchKernelGGL(k_residual<double>, dim3(Q), dim3(256), 0, s, (const cplx<double>*)y,
+                       (const cplx<double>*)ymeas, M, (cplx<double>*)r, stats);
+  else
+    hipLaunchKernelGGL(k_residual<float>, dim3(Q), dim3(256), 0, s, (const cplx<float>*)y, (const cplx<float>*)ymeas,
+                       M, (cplx<float>*)r, stats);
+  return hipGetLastError();
+}
+
+}  // namespace ls

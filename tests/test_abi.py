@@ -1,0 +1,66 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol declared in
+include/ls.h, and validates arguments on the host (no GPU work is enqueued by these calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1910_13844_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ls.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ls_[a-z_A-Z]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(L.EXPORTS) == declared_symbols()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libls.so not built")
+    return L.load()
+
+
+def test_all_symbols_exported(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def geom(**kw):
+    g = dict(n=32, p=4, kbh=1.0469375, xg=32.0, prec=0)
+    g.update(kw)
+    return L.Geom(g["n"], g["p"], g["kbh"], g["xg"], g["prec"], 0)
+
+
+def test_geometry_validation(lib):
+    b = C.c_size_t()
+    assert lib.ls_kernel_bytes(C.byref(geom()), C.byref(b)) == 0 and b.value > 0
+    assert lib.ls_kernel_bytes(C.byref(geom(kbh=3.2)), C.byref(b)) == -1       # Nyquist: k h < pi
+    assert lib.ls_kernel_bytes(C.byref(geom(p=3)), C.byref(b)) == -1           # p even
+    assert lib.ls_kernel_bytes(C.byref(geom(n=31)), C.byref(b)) == -1          # n even
+    assert lib.ls_kernel_bytes(C.byref(geom(xg=10.0)), C.byref(b)) == -1       # plane outside Omega
+    assert lib.ls_kernel_bytes(C.byref(geom(n=128, prec=1, xg=128.0)), C.byref(b)) == -3  # not built for c128
+    assert lib.ls_kernel_bytes(None, C.byref(b)) == -1
+
+
+def test_kernel_and_init_sizes(lib):
+    b, w = C.c_size_t(), C.c_size_t()
+    assert lib.ls_kernel_bytes(C.byref(geom(n=128, xg=128.0)), C.byref(b)) == 0
+    M = 256
+    assert b.value >= 129 * M * M * 8 + 129 * 128 * M * 8
+    assert lib.ls_init_workspace_bytes(C.byref(geom(n=128, xg=128.0)), C.byref(w)) == 0
+    assert w.value >= 2 * M ** 3 * 16
+
+
+def test_null_context_rejected(lib):
+    b = C.c_size_t()
+    assert lib.ls_workspace_bytes(None, 4, 0, C.byref(b)) == -1
+    assert lib.ls_forward(None, None, 1, None, None, None, None, None, 0, None) == -1
+    assert lib.ls_strerror(-2).decode().startswith("workspace")

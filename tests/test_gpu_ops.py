@@ -1,0 +1,96 @@
+"""GPU parity of the operators against the oracle (through the C ABI).
+
+Tolerances: complex128 path 1e-12 relative (FFT rounding ~ eps log N); complex64 path 2e-6
+relative for single operator applications (FP32 FFTs of length <= 256: ~ eps_32 sqrt(log N) per
+transform, 6 transforms).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import farfield, kernel, ops  # noqa: E402
+from paper_1910_13844_amd import api, workloads  # noqa: E402
+
+K = workloads.k_of()
+DEV = "cuda:0"
+_ctx = {}
+_gh = {}
+
+
+def ctx(n, prec):
+    key = (n, prec)
+    if key not in _ctx:
+        print(f"[ctx] n={n} prec={prec}", flush=True)
+        _ctx[key] = api.Context(n, K, p=4, xg=float(n), prec=prec, device=DEV)
+    return _ctx[key]
+
+
+def ghat(n):
+    if n not in _gh:
+        _gh[n] = kernel.ghat_m(n, 4, K)
+    return _gh[n]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def cdt(prec):
+    return torch.complex128 if prec == "c128" else torch.complex64
+
+
+@pytest.mark.parametrize("n,prec,tol", [(8, "c128", 1e-12), (16, "c128", 1e-12), (32, "c128", 1e-12),
+                                        (64, "c128", 1e-12), (96, "c128", 1e-12),
+                                        (16, "c64", 2e-6), (32, "c64", 2e-6), (64, "c64", 2e-6),
+                                        (96, "c64", 2e-6), (128, "c64", 2e-6)])
+def test_apply_G(n, prec, tol):
+    Q = 2
+    v = workloads.random_field(n, (Q, n, n, n))
+    c = ctx(n, prec)
+    out = c.ls_apply_G(torch.from_numpy(v).to(DEV, cdt(prec))).cpu().numpy()
+    for q in range(Q):
+        ref = ops.G_fft(ghat(n), v[q])
+        assert rel(out[q], ref) < tol, (n, prec, q, rel(out[q], ref))
+
+
+@pytest.mark.parametrize("n,prec,tol", [(16, "c128", 1e-12), (32, "c64", 2e-6)])
+def test_apply_A(n, prec, tol):
+    v = workloads.random_field(3, (1, n, n, n))
+    f = workloads.blob_potential(1, n, dn_max=0.05)
+    c = ctx(n, prec)
+    rd = torch.float64 if prec == "c128" else torch.float32
+    out = c.ls_apply_A(torch.from_numpy(f).to(DEV, rd), torch.from_numpy(v).to(DEV, cdt(prec))).cpu().numpy()
+    ref = ops.A_apply(ghat(n), f, v[0])
+    assert rel(out[0], ref) < tol
+
+
+@pytest.mark.parametrize("n,prec,tol", [(8, "c128", 1e-12), (16, "c128", 1e-12), (32, "c64", 2e-6), (64, "c64", 2e-6)])
+def test_farfield(n, prec, tol):
+    Q = 2
+    u = workloads.random_field(5, (Q, n, n, n))
+    f = workloads.blob_potential(2, n, dn_max=0.05)
+    c = ctx(n, prec)
+    rd = torch.float64 if prec == "c128" else torch.float32
+    y = c.ls_farfield(torch.from_numpy(f).to(DEV, rd), torch.from_numpy(u).to(DEV, cdt(prec))).cpu().numpy()
+    kern = farfield.slice_kernels(n, K, float(n))
+    for q in range(Q):
+        ref = farfield.farfield_fft(f * u[q], K, float(n), kern)
+        assert rel(y[q], ref) < tol, (q, rel(y[q], ref))
+    if n == 8:
+        assert rel(y[0], farfield.farfield_direct(f * u[0], K, float(n))) < tol
+
+
+@pytest.mark.parametrize("n,prec,tol", [(8, "c128", 1e-12), (32, "c64", 2e-6)])
+def test_farfield_adjoint(n, prec, tol):
+    r = workloads.random_field(6, (2, n, n))
+    c = ctx(n, prec)
+    rt = torch.from_numpy(r).to(DEV, cdt(prec))
+    out = c.ls_farfield_adj(rt, conj=False).cpu().numpy()
+    outc = c.ls_farfield_adj(rt, conj=True).cpu().numpy()
+    for q in range(2):
+        ref = farfield.farfield_T(r[q], K, float(n))
+        assert rel(out[q], ref) < tol
+        assert rel(outc[q], farfield.farfield_T(np.conj(r[q]), K, float(n))) < tol
