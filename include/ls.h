@@ -157,6 +157,14 @@ int ls_batch_poll(const ls_batch* b, int32_t* state, ls_solve_info* info);
 int ls_batch_release(ls_batch* b, int32_t slot);
 void ls_batch_destroy(ls_batch* b);
 
+/* Timing hook: enqueues `reps` launches of one pass of the solver iteration over Q slots of a
+ * LS_OP_FORWARD workspace, so a single kernel can be timed in isolation (the computation of the
+ * iteration, not a separate code path).  pass: 0 x-forward with the p-update prologue,
+ * 1 (y,z) plane convolution, 2 x-inverse with the v = p - G(f p) epilogue, 3 vector update.
+ * f [N] and u [Q][N] as for ls_forward; the workspace contents are overwritten. */
+int ls_profile_pass(const ls_ctx* ctx, const void* f, void* u, int32_t pass, int32_t Q, int32_t reps, void* ws,
+                    size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ EXPORTS = [
     "ls_strerror", "ls_last_error", "ls_kernel_bytes", "ls_init_workspace_bytes", "ls_green_init",
     "ls_ctx_destroy", "ls_workspace_bytes", "ls_apply_G", "ls_apply_A", "ls_forward", "ls_farfield",
     "ls_farfield_adj", "ls_vjp", "ls_grad", "ls_batch_bytes", "ls_batch_create", "ls_batch_admit",
-    "ls_batch_step", "ls_batch_poll", "ls_batch_release", "ls_batch_destroy",
+    "ls_batch_step", "ls_batch_poll", "ls_batch_release", "ls_batch_destroy", "ls_profile_pass",
 ]
 
 
@@ -80,6 +80,7 @@ def load() -> C.CDLL:
         "ls_batch_poll": (C.c_int, [vp, P(i32), P(SolveInfo)]),
         "ls_batch_release": (C.c_int, [vp, i32]),
         "ls_batch_destroy": (None, [vp]),
+        "ls_profile_pass": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -183,6 +183,14 @@ class Context:
         return loss.value, grad, [i.as_dict() for i in info]
 
 
+def profile_pass(ctx: "Context", f: torch.Tensor, u: torch.Tensor, pass_id: int, reps: int,
+                 ws: torch.Tensor, stream=None) -> None:
+    """ls_profile_pass: enqueue `reps` launches of one solver pass (for timing a kernel alone)."""
+    Q = u.numel() // ctx.N
+    L.check(ctx.lib.ls_profile_pass(ctx.h, _ptr(f), _ptr(u), int(pass_id), Q, int(reps), _ptr(ws), ws.numel(),
+                                    _stream(stream)), "ls_profile_pass")
+
+
 class Batch:
     """Slot pool for continuous batching (ls_batch_*)."""
 

@@ -620,6 +620,44 @@ int ls_grad(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, const
   return grad_driver(c, f, Q, dirs, nullptr, nullptr, y_meas, grad, loss, opts, info, ws, ws_bytes, stream);
 }
 
+int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32_t Q, int32_t reps, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !f || !u || !ws || Q < 1 || reps < 0 || pass < 0 || pass > 3) return LS_ERR_ARG;
+  const WsLayout L = ws_layout(c, Q, LS_OP_FORWARD);
+  if (ws_bytes < L.total) return LS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  std::vector<SlotDesc> d(Q);
+  ls_solve_opts o = opts_or_default(nullptr);
+  SlotState st0 = init_state(&o, ST_RUN);
+  st0.alpha[0] = st0.omega[0] = st0.beta[0] = 0.5;
+  std::vector<SlotState> st(Q, st0);
+  for (int i = 0; i < Q; ++i) {
+    d[i] = blank_desc(c, f);
+    d[i].vec[V_X] = (char*)u + (size_t)i * c->N * c->csz;
+    bind_solver(c, w, L, i, 0, d[i]);
+  }
+  Run r = make_run(c, w, L, Q, 0, s);
+  int rc = upload(r, d, &st);
+  if (rc) return rc;
+  PassArgs a = r.base();
+  a.mask = M_RUN;
+  for (int it = 0; it < reps; ++it) {
+    if (pass == 0) {
+      a.mode = PRO_P;
+      HIPCHK(launch_xfwd(c->dbl, c->n, a, s));
+    } else if (pass == 1) {
+      HIPCHK(launch_yz(c->dbl, c->n, a, s));
+    } else if (pass == 2) {
+      a.mode = EPI_AXV;
+      HIPCHK(launch_xinv(c->dbl, c->n, a, s));
+    } else {
+      HIPCHK(launch_update(c->dbl, c->n, a, s));
+    }
+  }
+  return LS_OK;
+}
+
 }  // extern "C"
 
 // =============================================================================================
