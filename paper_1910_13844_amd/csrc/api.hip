@@ -54,10 +54,10 @@ constexpr uint32_t M_ALL = (1u << ST_RUN) | (1u << ST_HALF) | (1u << ST_CHECK) |
 // Vectors per slot (each N complex) for each operation; the x-spectrum takes two.
 int vecs_per_slot(int op) {
   switch (op) {
-    case LS_OP_FORWARD: return 8;   // r rh p v s t + spectrum(2)
+    case LS_OP_FORWARD: return 12;  // r rh p v s t + spectra (3 x 2)
     case LS_OP_FARFIELD: return 3;  // spectrum(2) + detector x-spectrum
-    case LS_OP_GRAD: return 11;     // u wbar b r rh p v s t + spectrum(2)
-    default: return 2;              // spectrum
+    case LS_OP_GRAD: return 15;     // u wbar b r rh p v s t + spectra (3 x 2)
+    default: return 6;              // spectra (3 x 2)
   }
 }
 
@@ -122,6 +122,7 @@ struct Run {
     a.tw = c->tw;
     a.kern = c->kvol;
     a.spec = V_SPEC;
+    a.spec2 = -1;
     return a;
   }
 };
@@ -136,6 +137,9 @@ int matvec(const Run& r, int pro, int sel, int epi, int esel, int esel2, uint32_
   a.mode = epi;
   a.sel = esel;
   a.sel2 = esel2;
+  const bool split = yz_split() || r.c->n == 96;
+  a.spec = split ? V_SPE : V_SPEC;
+  a.spec2 = split ? V_SPO : -1;
   HIPCHK(launch_xinv(r.c->dbl, r.c->n, a, r.s));
   return LS_OK;
 }
@@ -281,6 +285,8 @@ void bind_solver(const ls_ctx* c, char* ws, const WsLayout& L, int slot, int k0,
   d.vec[V_S] = vptr(c, ws, L, slot, k0 + 4);
   d.vec[V_T] = vptr(c, ws, L, slot, k0 + 5);
   d.vec[V_SPEC] = vptr(c, ws, L, slot, k0 + 6);
+  d.vec[V_SPE] = vptr(c, ws, L, slot, k0 + 8);
+  d.vec[V_SPO] = vptr(c, ws, L, slot, k0 + 10);
 }
 
 int check_ctx(const ls_ctx* c) { return c && c->kbuf ? LS_OK : LS_ERR_ARG; }
@@ -421,6 +427,8 @@ static int apply_common(const ls_ctx* c, const void* f, const void* v, void* out
       d[i].vec[V_X] = (char*)v + (size_t)(q0 + i) * c->N * c->csz;
       d[i].vec[V_R] = (char*)out + (size_t)(q0 + i) * c->N * c->csz;
       d[i].vec[V_SPEC] = vptr(c, w, L, i, 0);
+      d[i].vec[V_SPE] = vptr(c, w, L, i, 2);
+      d[i].vec[V_SPO] = vptr(c, w, L, i, 4);
     }
     Run r = make_run(c, w, L, nq, 0, s);
     int rc = upload(r, d, &st);
@@ -650,6 +658,9 @@ int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32
       HIPCHK(launch_yz(c->dbl, c->n, a, s));
     } else if (pass == 2) {
       a.mode = EPI_AXV;
+      const bool split = yz_split() || c->n == 96;
+      a.spec = split ? V_SPE : V_SPEC;
+      a.spec2 = split ? V_SPO : -1;
       HIPCHK(launch_xinv(c->dbl, c->n, a, s));
     } else {
       HIPCHK(launch_update(c->dbl, c->n, a, s));

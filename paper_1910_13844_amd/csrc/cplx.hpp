@@ -50,12 +50,19 @@ __device__ __forceinline__ void dot_acc(cplx<double>& acc, cplx<T> a, cplx<T> b)
   acc.im += ar * bi - ai * br;
 }
 
-// Orders all LDS traffic of a wavefront around this point.  LDS operations of one wavefront
-// execute in issue order, so this is enough for lanes of one wavefront to exchange data.
+// Orders the LDS traffic of a wavefront around this point for lanes that exchange data through
+// LDS.  The LDS unit executes the DS instructions of one wavefront in issue order, so it is
+// enough that the compiler keeps their program order here: a compiler barrier plus the
+// wave-level scheduling barrier, without a hardware wait on outstanding LDS operations.
 __device__ __forceinline__ void wave_sync() {
+#ifdef LS_WAVE_FENCE
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#else
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+#endif
 }
 
 __device__ __forceinline__ double shfl_down_d(double v, int off) {

@@ -149,4 +149,108 @@ __device__ __forceinline__ void fft_group(cplx<T>* base, int stride, int lane, c
     stockham_pass<T, N, E, P::R[4], P::R[0] * P::R[1] * P::R[2] * P::R[3], DIR, TWS>(base, stride, lane, tw);
 }
 
+// ---------------------------------------------------------------------------------------------
+// 16-point DFT in registers as 4 x 4 with internal twiddles exp(DIR 2 pi i m / 16).
+template <int DIR, typename T>
+struct SmallDFT<16, DIR, T> {
+  static __device__ __forceinline__ void run(cplx<T>* a) {
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
+    // w16^m for m = 0..9
+    const cplx<T> w[10] = {{(T)1, (T)0},       {c1, DIR * s1},  {h, DIR * h},     {s1, DIR * c1},   {(T)0, (T)DIR},
+                           {-s1, DIR * c1},    {-h, DIR * h},   {-c1, DIR * s1},  {(T)-1, (T)0},    {-c1, -DIR * s1}};
+    cplx<T> b[16];
+#pragma unroll
+    for (int j1 = 0; j1 < 4; ++j1) {
+      cplx<T> t[4] = {a[j1], a[j1 + 4], a[j1 + 8], a[j1 + 12]};
+      SmallDFT<4, DIR, T>::run(t);
+      b[j1 * 4 + 0] = t[0];
+#pragma unroll
+      for (int k = 1; k < 4; ++k) b[j1 * 4 + k] = j1 == 0 ? t[k] : t[k] * w[j1 * k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cplx<T> t[4] = {b[k], b[4 + k], b[8 + k], b[12 + k]};
+      SmallDFT<4, DIR, T>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) a[k + 4 * k2] = t[k2];
+    }
+  }
+};
+
+template <int DIR, typename T>
+struct SmallDFT<1, DIR, T> {
+  static __device__ __forceinline__ void run(cplx<T>*) {}
+};
+
+// ---------------------------------------------------------------------------------------------
+// Register-resident transforms with a single LDS transpose (four-step, N = L * E).
+// Layout A: lane l in [0, L) holds a[j] = x[l + L j], j < E (natural index l + L j).
+// Layout B: lane l holds a[t L + k2] = X[k1 + E k2] for k1 = l P + t (t < P = E / L), k2 < L.
+// fft_a2b maps layout A data to its transform in layout B; fft_b2a is the inverse structure
+// (layout B spectrum -> layout A signal).  Both are unnormalised, with sign DIR.  The L lanes
+// of a transform must sit in one wavefront; `buf` (N entries at stride s) is scratch for the
+// transpose and may alias the data's own LDS storage.
+template <int N>
+struct Split;
+template <> struct Split<8>   { static constexpr int L = 1, E = 8; };
+template <> struct Split<16>  { static constexpr int L = 2, E = 8; };
+template <> struct Split<32>  { static constexpr int L = 4, E = 8; };
+template <> struct Split<64>  { static constexpr int L = 8, E = 8; };
+template <> struct Split<128> { static constexpr int L = 8, E = 16; };
+template <> struct Split<256> { static constexpr int L = 16, E = 16; };
+
+template <int N>
+__device__ __forceinline__ int tpos(int k1, int m) {
+  // position of T[k1][m] in the scratch: row k1, column m swizzled by the reading lane
+  constexpr int L = Split<N>::L, P = Split<N>::E / Split<N>::L;
+  return k1 * L + (m ^ ((k1 / P) & (L - 1)));
+}
+
+template <typename T, int DIR, int TWS>
+__device__ __forceinline__ cplx<T> twid(const cplx<T>* tw, int m) {
+  cplx<T> w = tw[m * TWS];
+  if (DIR > 0) w.im = -w.im;
+  return w;
+}
+
+template <typename T, int N, int DIR, int TWS>
+__device__ __forceinline__ void fft_a2b(cplx<T> (&a)[Split<N>::E], cplx<T>* buf, int s, int lane, const cplx<T>* tw) {
+  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+  SmallDFT<E, DIR, T>::run(a);
+  if constexpr (L > 1) {
+#pragma unroll
+    for (int k1 = 1; k1 < E; ++k1) a[k1] = a[k1] * twid<T, DIR, TWS>(tw, lane * k1);
+    wave_sync();
+#pragma unroll
+    for (int k1 = 0; k1 < E; ++k1) buf[tpos<N>(k1, lane) * s] = a[k1];
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int m = 0; m < L; ++m) a[t * L + m] = buf[tpos<N>(lane * P + t, m) * s];
+#pragma unroll
+    for (int t = 0; t < P; ++t) SmallDFT<L, DIR, T>::run(&a[t * L]);
+  }
+}
+
+template <typename T, int N, int DIR, int TWS>
+__device__ __forceinline__ void fft_b2a(cplx<T> (&a)[Split<N>::E], cplx<T>* buf, int s, int lane, const cplx<T>* tw) {
+  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+  if constexpr (L > 1) {
+#pragma unroll
+    for (int t = 0; t < P; ++t) SmallDFT<L, DIR, T>::run(&a[t * L]);
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int m = 0; m < L; ++m) buf[tpos<N>(lane * P + t, m) * s] = a[t * L + m];
+    wave_sync();
+#pragma unroll
+    for (int k1 = 0; k1 < E; ++k1) a[k1] = buf[tpos<N>(k1, lane) * s];
+#pragma unroll
+    for (int k1 = 1; k1 < E; ++k1) a[k1] = a[k1] * twid<T, DIR, TWS>(tw, lane * k1);
+  }
+  SmallDFT<E, DIR, T>::run(a);
+}
+
 }  // namespace ls

@@ -18,7 +18,9 @@ enum Vec : int {
   V_SPEC = 7,  // x-spectrum scratch: [2n kx][nz][n y]
   V_B = 8,     // stored right-hand side (null: plane wave)
   V_AUX = 9,   // detector-plane buffer or other per-slot I/O
-  V_COUNT = 10
+  V_SPE = 10,  // (y,z)-convolved x-spectrum, even-ky half
+  V_SPO = 11,  // (y,z)-convolved x-spectrum, odd-ky half
+  V_COUNT = 12
 };
 
 struct SlotDesc {
@@ -82,6 +84,7 @@ struct PassArgs {
   int mode;          // prologue / epilogue
   int sel, sel2;
   int spec;          // vector holding the x-spectrum read or written by the pass
+  int spec2;         // k_xinv: second half to combine (odd ky), or -1
   const void* tw;    // twiddle table exp(-2 pi i m / 2n), m < 2n
   const void* kern;  // Fourier kernel (pass-specific layout)
 };

@@ -23,10 +23,23 @@
 
 namespace ls {
 
+// Device-memory accessors.  Slot vectors are reached through descriptor pointers, which the
+// compiler cannot prove global; the casts make it emit global (not flat) memory instructions,
+// so LDS waits inside the transforms do not also wait for outstanding HBM loads.
+#define LS_GLOBAL __attribute__((address_space(1)))
 template <typename T>
-__device__ __forceinline__ cplx<T> ld(const void* p, size_t i) { return ((const cplx<T>*)p)[i]; }
+__device__ __forceinline__ cplx<T> ld(const void* p, size_t i) {
+  const LS_GLOBAL T* q = (const LS_GLOBAL T*)p;
+  return cplx<T>{q[2 * i], q[2 * i + 1]};
+}
 template <typename T>
-__device__ __forceinline__ void stv(void* p, size_t i, cplx<T> v) { ((cplx<T>*)p)[i] = v; }
+__device__ __forceinline__ void stv(void* p, size_t i, cplx<T> v) {
+  LS_GLOBAL T* q = (LS_GLOBAL T*)p;
+  q[2 * i] = v.re;
+  q[2 * i + 1] = v.im;
+}
+template <typename T>
+__device__ __forceinline__ T ldr(const void* p, size_t i) { return ((const LS_GLOBAL T*)p)[i]; }
 
 __device__ __forceinline__ bool slot_active(const PassArgs& a, int slot) {
   return (a.mask >> a.st[slot].status) & 1u;
@@ -64,13 +77,68 @@ __device__ __forceinline__ double* part_ptr(const PassArgs& a, int slot, int blk
 }
 
 // =============================================================================================
+// Row transforms of length N held in LDS (stride 1), natural order in and out, by L lanes.
+template <int N>
+struct HasSplit {
+  static constexpr bool value = (N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256);
+};
+
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void row_fft(cplx<T>* row, int lane, const cplx<T>* tw) {
+  if constexpr (HasSplit<N>::value) {
+    constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+    cplx<T> v[E];
+    if (DIR < 0) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = row[lane + L * j];
+      fft_a2b<T, N, DIR, 2>(v, row, 1, lane, tw);
+      wave_sync();
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+#pragma unroll
+        for (int k2 = 0; k2 < L; ++k2) row[(lane * P + t) + E * k2] = v[t * L + k2];
+    } else {
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+#pragma unroll
+        for (int k2 = 0; k2 < L; ++k2) v[t * L + k2] = row[(lane * P + t) + E * k2];
+      fft_b2a<T, N, DIR, 2>(v, row, 1, lane, tw);
+      wave_sync();
+#pragma unroll
+      for (int j = 0; j < E; ++j) row[lane + L * j] = v[j];
+    }
+    wave_sync();
+  } else {
+    fft_group<T, N, DIR, 2>(row, 1, lane, tw);
+  }
+}
+
+template <int N>
+constexpr int row_lanes() {
+  if constexpr (HasSplit<N>::value)
+    return Split<N>::L;
+  else
+    return Lanes<N>::value;
+}
+
+template <int N>
+struct XCfg {
+  static constexpr int TY = N < 16 ? N : 16;
+  static constexpr int NYT = N / TY;
+  static constexpr int PITCH = N + 1;
+  static constexpr int IT = (TY * N + 255) / 256;       // elements per thread, [y][x] tile
+  static constexpr int IT2 = (2 * N * TY + 255) / 256;  // elements per thread, [kx][y] tile
+};
+
+// =============================================================================================
 // k_xfwd: prologue, zero-extension n -> 2n along x and the two n-point x-DFTs of each row.
-template <typename T, int N>
+// Every global load of a thread is issued before the first use (unrolled), so the loads of a
+// wavefront overlap instead of paying the memory latency one at a time.
+template <typename T, int N, int MODE>
 __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
-  constexpr int TY = N < 16 ? N : 16;
-  constexpr int NYT = N / TY;
-  constexpr int PITCH = N + 1;
-  constexpr int L = Lanes<N>::value;
+  using X = XCfg<N>;
+  constexpr int TY = X::TY, NYT = X::NYT, PITCH = X::PITCH, IT = X::IT, IT2 = X::IT2;
+  constexpr int L = row_lanes<N>();
   constexpr int NG = 256 / L;
   __shared__ cplx<T> bufE[TY * PITCH];
   __shared__ cplx<T> bufO[TY * PITCH];
@@ -86,65 +154,89 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
   const SlotDesc& d = a.desc[slot];
   const SlotState& st = a.st[slot];
   for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
-  __syncthreads();
 
   const size_t row0 = ((size_t)z * N + y0) * N;
-  const T* f = (const T*)d.f;
-  const int mode = a.mode;
+  constexpr bool HAS_F = !(MODE == PRO_VEC || MODE == PRO_CONJ_VEC);
+  cplx<T> r0[IT], r1[IT], r2[IT];
+  T ff[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = tid + it * 256;
+    if (i < TY * N) {
+      const size_t idx = row0 + i;
+      if constexpr (MODE == PRO_F_VEC || MODE == PRO_VEC || MODE == PRO_CONJ_VEC) r0[it] = ld<T>(d.vec[a.sel], idx);
+      if constexpr (MODE == PRO_P || MODE == PRO_S) {
+        r0[it] = ld<T>(d.vec[V_R], idx);
+        r2[it] = ld<T>(d.vec[V_V], idx);
+      }
+      if constexpr (MODE == PRO_P) r1[it] = ld<T>(d.vec[V_P], idx);
+      if constexpr (MODE == PRO_F_B) {
+        if (d.vec[V_B]) r0[it] = ld<T>(d.vec[V_B], idx);
+      }
+      if constexpr (HAS_F) ff[it] = ldr<T>(d.f, idx);
+    }
+  }
   const cplx<T> alpha = scal<T>(st.alpha), beta = scal<T>(st.beta), omega = scal<T>(st.omega);
   const bool restart = st.restart_flag != 0;
-  void* vin = d.vec[a.sel];
   double ss = 0.0;
-  for (int i = tid; i < TY * N; i += 256) {
-    const int yy = i / N;
-    const int x = i - yy * N;
-    const size_t idx = row0 + i;
-    cplx<T> w;
-    if (mode == PRO_F_VEC) {
-      w = f[idx] * ld<T>(vin, idx);
-    } else if (mode == PRO_F_B) {
-      w = f[idx] * rhs_b<T>(d, N, idx, z, y0 + yy, x);
-    } else if (mode == PRO_P) {
-      const cplx<T> r = ld<T>(d.vec[V_R], idx);
-      cplx<T> p;
-      if (restart) {
-        p = r;
-        stv<T>(d.vec[V_RH], idx, r);
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = tid + it * 256;
+    if (i < TY * N) {
+      const int yy = i / N;
+      const int x = i - yy * N;
+      const size_t idx = row0 + i;
+      cplx<T> w;
+      if constexpr (MODE == PRO_F_VEC) {
+        w = ff[it] * r0[it];
+      } else if constexpr (MODE == PRO_F_B) {
+        w = ff[it] * (d.vec[V_B] ? r0[it] : plane_wave<T>(d, N, z, y0 + yy, x));
+      } else if constexpr (MODE == PRO_P) {
+        cplx<T> p;
+        if (restart) {
+          p = r0[it];
+          stv<T>(d.vec[V_RH], idx, p);
+        } else {
+          p = r0[it] + beta * (r1[it] - omega * r2[it]);
+        }
+        stv<T>(d.vec[V_P], idx, p);
+        w = ff[it] * p;
+      } else if constexpr (MODE == PRO_S) {
+        const cplx<T> sv = r0[it] - alpha * r2[it];
+        stv<T>(d.vec[V_S], idx, sv);
+        ss += (double)sv.re * sv.re + (double)sv.im * sv.im;
+        w = ff[it] * sv;
+      } else if constexpr (MODE == PRO_VEC) {
+        w = r0[it];
       } else {
-        p = r + beta * (ld<T>(d.vec[V_P], idx) - omega * ld<T>(d.vec[V_V], idx));
+        w = conj(r0[it]);
       }
-      stv<T>(d.vec[V_P], idx, p);
-      w = f[idx] * p;
-    } else if (mode == PRO_S) {
-      const cplx<T> s = ld<T>(d.vec[V_R], idx) - alpha * ld<T>(d.vec[V_V], idx);
-      stv<T>(d.vec[V_S], idx, s);
-      ss += (double)s.re * s.re + (double)s.im * s.im;
-      w = f[idx] * s;
-    } else if (mode == PRO_VEC) {
-      w = ld<T>(vin, idx);
-    } else {
-      w = conj(ld<T>(vin, idx));
+      bufE[yy * PITCH + x] = w;
+      bufO[yy * PITCH + x] = w * tw[x];
     }
-    bufE[yy * PITCH + x] = w;
-    bufO[yy * PITCH + x] = w * tw[x];
   }
   __syncthreads();
   {
     const int g = tid / L, lane = tid - (tid / L) * L;
     for (int t = g; t < 2 * TY; t += NG) {
       cplx<T>* base = t < TY ? bufE + t * PITCH : bufO + (t - TY) * PITCH;
-      fft_group<T, N, -1, 2>(base, 1, lane, tw);
+      row_fft<T, N, -1>(base, lane, tw);
     }
   }
   __syncthreads();
-  cplx<T>* spec = (cplx<T>*)d.vec[a.spec];
-  for (int i = tid; i < 2 * N * TY; i += 256) {
-    const int yy = i % TY;
-    const int kx = i / TY;
-    const cplx<T>* src = (kx & 1) ? bufO : bufE;
-    spec[((size_t)kx * a.nz + z) * N + y0 + yy] = src[yy * PITCH + (kx >> 1)];
+  void* spec = d.vec[a.spec];
+#pragma unroll
+  for (int it = 0; it < IT2; ++it) {
+    const int i = tid + it * 256;
+    if (i < 2 * N * TY) {
+      const int yy = i % TY;
+      const int kx = i / TY;
+      const cplx<T>* src = (kx & 1) ? bufO : bufE;
+      stv<T>(spec, ((size_t)kx * a.nz + z) * N + y0 + yy, src[yy * PITCH + (kx >> 1)]);
+    }
   }
-  if (mode == PRO_S) {
+  if constexpr (MODE == PRO_S) {
     double v[1] = {ss};
     block_sum<1>(v, red);
     if (tid == 0) {
@@ -157,12 +249,11 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
 
 // =============================================================================================
 // k_xinv: inverse x-DFTs (even + modulated odd half), crop to n, epilogue and FP64 partials.
-template <typename T, int N>
+template <typename T, int N, int EPI>
 __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
-  constexpr int TY = N < 16 ? N : 16;
-  constexpr int NYT = N / TY;
-  constexpr int PITCH = N + 1;
-  constexpr int L = Lanes<N>::value;
+  using X = XCfg<N>;
+  constexpr int TY = X::TY, NYT = X::NYT, PITCH = X::PITCH, IT = X::IT, IT2 = X::IT2;
+  constexpr int L = row_lanes<N>();
   constexpr int NG = 256 / L;
   __shared__ cplx<T> bufE[TY * PITCH];
   __shared__ cplx<T> bufO[TY * PITCH];
@@ -177,67 +268,109 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   const int y0 = (blk - z * NYT) * TY;
   const SlotDesc& d = a.desc[slot];
   for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
-  const cplx<T>* spec = (const cplx<T>*)d.vec[a.spec];
-  for (int i = tid; i < 2 * N * TY; i += 256) {
-    const int yy = i % TY;
-    const int kx = i / TY;
-    cplx<T>* dst = (kx & 1) ? bufO : bufE;
-    dst[yy * PITCH + (kx >> 1)] = spec[((size_t)kx * a.nz + z) * N + y0 + yy];
+  {
+    const void* spec = d.vec[a.spec];
+    const void* spo = a.spec2 >= 0 ? d.vec[a.spec2] : nullptr;
+    cplx<T> e[IT2], o[IT2];
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int i = tid + it * 256;
+      if (i < 2 * N * TY) {
+        const size_t gi = ((size_t)(i / TY) * a.nz + z) * N + y0 + i % TY;
+        e[it] = ld<T>(spec, gi);
+        if (spo) o[it] = ld<T>(spo, gi);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int i = tid + it * 256;
+      if (i < 2 * N * TY) {
+        const int yy = i % TY;
+        const int kx = i / TY;
+        // y-parity halves of the (y,z) convolution: value = E + exp(+i pi y / n) O
+        const cplx<T> v = spo ? e[it] + mulc(o[it], tw[y0 + yy]) : e[it];
+        ((kx & 1) ? bufO : bufE)[yy * PITCH + (kx >> 1)] = v;
+      }
+    }
   }
   __syncthreads();
   {
     const int g = tid / L, lane = tid - (tid / L) * L;
     for (int t = g; t < 2 * TY; t += NG) {
       cplx<T>* base = t < TY ? bufE + t * PITCH : bufO + (t - TY) * PITCH;
-      fft_group<T, N, +1, 2>(base, 1, lane, tw);
+      row_fft<T, N, +1>(base, lane, tw);
     }
   }
   __syncthreads();
   const size_t row0 = ((size_t)z * N + y0) * N;
-  const int mode = a.mode;
-  cplx<double> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
-  for (int i = tid; i < TY * N; i += 256) {
-    const int yy = i / N;
-    const int x = i - yy * N;
-    const size_t idx = row0 + i;
-    const cplx<T> g = bufE[yy * PITCH + x] + mulc(bufO[yy * PITCH + x], tw[x]);
-    if (mode == EPI_STORE) {
-      stv<T>(d.vec[a.sel], idx, g);
-    } else if (mode == EPI_AXV) {
-      const cplx<T> v = ld<T>(d.vec[V_P], idx) - g;
-      stv<T>(d.vec[V_V], idx, v);
-      dot_acc(a0, ld<T>(d.vec[V_RH], idx), v);
-    } else if (mode == EPI_AXT) {
-      const cplx<T> s = ld<T>(d.vec[V_S], idx);
-      const cplx<T> t = s - g;
-      stv<T>(d.vec[V_T], idx, t);
-      dot_acc(a1, t, s);
-      a2.re += (double)t.re * t.re + (double)t.im * t.im;
-    } else if (mode == EPI_R0) {
-      const cplx<T> b = rhs_b<T>(d, N, idx, z, y0 + yy, x);
-      stv<T>(d.vec[V_X], idx, b);
-      stv<T>(d.vec[V_R], idx, g);
-      stv<T>(d.vec[V_RH], idx, g);
-      a0.re += (double)g.re * g.re + (double)g.im * g.im;
-      a1.re += (double)b.re * b.re + (double)b.im * b.im;
-    } else if (mode == EPI_TRUE) {
-      const cplx<T> b = rhs_b<T>(d, N, idx, z, y0 + yy, x);
-      const cplx<T> r = (b - ld<T>(d.vec[V_X], idx)) + g;
-      stv<T>(d.vec[V_R], idx, r);
-      a0.re += (double)r.re * r.re + (double)r.im * r.im;
-    } else {  // EPI_AX
-      stv<T>(d.vec[a.sel2], idx, ld<T>(d.vec[a.sel], idx) - g);
+  cplx<T> q0[IT], q1[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = tid + it * 256;
+    if (i < TY * N) {
+      const size_t idx = row0 + i;
+      if constexpr (EPI == EPI_AXV) {
+        q0[it] = ld<T>(d.vec[V_P], idx);
+        q1[it] = ld<T>(d.vec[V_RH], idx);
+      } else if constexpr (EPI == EPI_AXT) {
+        q0[it] = ld<T>(d.vec[V_S], idx);
+      } else if constexpr (EPI == EPI_R0) {
+        if (d.vec[V_B]) q0[it] = ld<T>(d.vec[V_B], idx);
+      } else if constexpr (EPI == EPI_TRUE) {
+        if (d.vec[V_B]) q0[it] = ld<T>(d.vec[V_B], idx);
+        q1[it] = ld<T>(d.vec[V_X], idx);
+      } else if constexpr (EPI == EPI_AX) {
+        q0[it] = ld<T>(d.vec[a.sel], idx);
+      }
     }
   }
-  if (mode == EPI_AXV || mode == EPI_AXT || mode == EPI_R0 || mode == EPI_TRUE) {
+  cplx<double> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = tid + it * 256;
+    if (i < TY * N) {
+      const int yy = i / N;
+      const int x = i - yy * N;
+      const size_t idx = row0 + i;
+      const cplx<T> g = bufE[yy * PITCH + x] + mulc(bufO[yy * PITCH + x], tw[x]);
+      if constexpr (EPI == EPI_STORE) {
+        stv<T>(d.vec[a.sel], idx, g);
+      } else if constexpr (EPI == EPI_AXV) {
+        const cplx<T> v = q0[it] - g;
+        stv<T>(d.vec[V_V], idx, v);
+        dot_acc(a0, q1[it], v);
+      } else if constexpr (EPI == EPI_AXT) {
+        const cplx<T> t = q0[it] - g;
+        stv<T>(d.vec[V_T], idx, t);
+        dot_acc(a1, t, q0[it]);
+        a2.re += (double)t.re * t.re + (double)t.im * t.im;
+      } else if constexpr (EPI == EPI_R0) {
+        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, y0 + yy, x);
+        stv<T>(d.vec[V_X], idx, b);
+        stv<T>(d.vec[V_R], idx, g);
+        stv<T>(d.vec[V_RH], idx, g);
+        a0.re += (double)g.re * g.re + (double)g.im * g.im;
+        a1.re += (double)b.re * b.re + (double)b.im * b.im;
+      } else if constexpr (EPI == EPI_TRUE) {
+        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, y0 + yy, x);
+        const cplx<T> r = (b - q1[it]) + g;
+        stv<T>(d.vec[V_R], idx, r);
+        a0.re += (double)r.re * r.re + (double)r.im * r.im;
+      } else {  // EPI_AX
+        stv<T>(d.vec[a.sel2], idx, q0[it] - g);
+      }
+    }
+  }
+  if constexpr (EPI == EPI_AXV || EPI == EPI_AXT || EPI == EPI_R0 || EPI == EPI_TRUE) {
     double v[6] = {a0.re, a0.im, a1.re, a1.im, a2.re, a2.im};
     block_sum<6>(v, red);
     if (tid == 0) {
-      if (mode == EPI_AXV || mode == EPI_TRUE) {
+      if constexpr (EPI == EPI_AXV || EPI == EPI_TRUE) {
         double* pp = part_ptr(a, slot, blk, 0);
         pp[0] = v[0];
         pp[1] = v[1];
-      } else if (mode == EPI_R0) {
+      } else if constexpr (EPI == EPI_R0) {
         double* pp = part_ptr(a, slot, blk, 0);
         pp[0] = v[0];
         pp[1] = 0.0;
@@ -329,7 +462,8 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_yz(PassArgs a) {
   const int tid = threadIdx.x;
   const SlotDesc& d = a.desc[slot];
   for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
-  cplx<T>* S = (cplx<T>*)d.vec[a.spec] + (size_t)kx * N * N;
+  void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
   const int kxp = kx <= N ? kx : 2 * N - kx;
   const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
   const int g = tid / L, lane = tid - (tid / L) * L;
@@ -341,7 +475,7 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_yz(PassArgs a) {
     for (int j = 0; j < PER; ++j) {
       const int i = tid + j * NT;
       const int zz = i / N, y = i - zz * N;
-      cplx<T> v = S[i];
+      cplx<T> v = ld<T>(Sv, soff + i);
       if (par) v = v * tw[y];
       plane[zz * PITCH + y] = v;
     }
@@ -359,9 +493,263 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_yz(PassArgs a) {
       if (par == 0)
         acc[j] = plane[zz * PITCH + y];
       else
-        S[i] = acc[j] + mulc(plane[zz * PITCH + y], tw[y]);
+        stv<T>(Sv, soff + i, acc[j] + mulc(plane[zz * PITCH + y], tw[y]));
     }
     __syncthreads();
+  }
+}
+
+// z-convolution of one column with four-step transforms; the kernel coefficients of both
+// z-parities are requested before the forward transform so their latency overlaps it.
+template <typename T>
+struct alignas(4 * sizeof(T)) cpair {
+  cplx<T> a, b;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void zconv4(cplx<T>* col, int lane, const cplx<T>* tw, const cplx<T>* kr) {
+  constexpr int PITCH = N + 1;
+  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+  const LS_GLOBAL T* k2p = (const LS_GLOBAL T*)kr;
+  cplx<T> e[E], o[E];
+  cpair<T> kk[E];
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+#pragma unroll
+    for (int k2 = 0; k2 < L; ++k2) {
+      const LS_GLOBAL T* q = k2p + 4 * (lane * P + t + E * k2);
+      kk[t * L + k2] = cpair<T>{{q[0], q[1]}, {q[2], q[3]}};
+    }
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int zz = lane + L * j;
+    e[j] = col[zz * PITCH];
+    o[j] = e[j] * tw[zz];
+  }
+  fft_a2b<T, N, -1, 2>(e, col, PITCH, lane, tw);
+#pragma unroll
+  for (int j = 0; j < E; ++j) e[j] = e[j] * kk[j].a;
+  fft_b2a<T, N, +1, 2>(e, col, PITCH, lane, tw);
+  fft_a2b<T, N, -1, 2>(o, col, PITCH, lane, tw);
+#pragma unroll
+  for (int j = 0; j < E; ++j) o[j] = o[j] * kk[j].b;
+  fft_b2a<T, N, +1, 2>(o, col, PITCH, lane, tw);
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int zz = lane + L * j;
+    col[zz * PITCH] = e[j] + mulc(o[j], tw[zz]);
+  }
+}
+
+// k_yz2: the same (y, z) convolution with register-resident four-step transforms (one LDS
+// transpose per transform).  The forward z-DFT, the kernel multiply and the inverse z-DFT of a
+// column run between two transposes without leaving registers; the even-ky result is held in
+// registers while the odd-ky half is computed.  Rows and columns are handed to lane groups with
+// spacing 2 so that a wavefront's LDS accesses spread over the banks.
+template <int N>
+struct Plane2Cfg {
+  static constexpr int NT = N >= 128 ? 512 : (N * N >= 256 ? 256 : N * N);
+  static constexpr int PITCH = N + 1;
+};
+
+template <int N>
+__device__ __forceinline__ int spread2(int idx) {
+  return 2 * (idx % (N / 2)) + idx / (N / 2);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(Plane2Cfg<N>::NT) void k_yz2(PassArgs a) {
+  constexpr int NT = Plane2Cfg<N>::NT, PITCH = Plane2Cfg<N>::PITCH;
+  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+  constexpr int G = NT / L;
+  constexpr int RR = (N + G - 1) / G;
+  __shared__ cplx<T> plane[N * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  int kx, slot;
+  plane_decode(a, kx, slot);
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
+  const int g = tid / L, lane = tid - g * L;
+  cplx<T> acc[RR][E];
+  __syncthreads();
+  constexpr int PER = N * N / NT;
+#pragma unroll 1
+  for (int par = 0; par < 2; ++par) {
+    {
+      cplx<T> ldv[PER];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) ldv[j] = ld<T>(Sv, soff + tid + j * NT);
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int i = tid + j * NT;
+        const int zz = i / N, y = i - zz * N;
+        plane[zz * PITCH + y] = par ? ldv[j] * tw[y] : ldv[j];
+      }
+    }
+    __syncthreads();
+    // forward y-DFT of every z-row (natural-order output)
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr) {
+      const int idx = g + rr * G;
+      if (idx < N) {
+        cplx<T>* row = plane + spread2<N>(idx) * PITCH;
+        cplx<T> v[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = row[lane + L * j];
+        fft_a2b<T, N, -1, 2>(v, row, 1, lane, tw);
+        wave_sync();
+#pragma unroll
+        for (int t = 0; t < P; ++t)
+#pragma unroll
+          for (int k2 = 0; k2 < L; ++k2) row[(lane * P + t) + E * k2] = v[t * L + k2];
+      }
+    }
+    __syncthreads();
+    // z-convolution of every ky column
+    for (int idx = g; idx < N; idx += G) {
+      const int c = spread2<N>(idx);
+      zconv4<T, N>(plane + c, lane, tw, K + (size_t)(2 * c + par) * (2 * N));
+    }
+    __syncthreads();
+    // inverse y-DFT of every z-row; the even half waits in registers for the odd half
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr) {
+      const int idx = g + rr * G;
+      if (idx < N) {
+        cplx<T>* row = plane + spread2<N>(idx) * PITCH;
+        cplx<T> v[E];
+#pragma unroll
+        for (int t = 0; t < P; ++t)
+#pragma unroll
+          for (int k2 = 0; k2 < L; ++k2) v[t * L + k2] = row[(lane * P + t) + E * k2];
+        fft_b2a<T, N, +1, 2>(v, row, 1, lane, tw);
+        if (par == 0) {
+#pragma unroll
+          for (int j = 0; j < E; ++j) acc[rr][j] = v[j];
+        } else {
+          wave_sync();
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            const int y = lane + L * j;
+            row[y] = acc[rr][j] + mulc(v[j], tw[y]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < N * N; i += NT) {
+    const int zz = i / N, y = i - zz * N;
+    stv<T>(Sv, soff + i, plane[zz * PITCH + y]);
+  }
+}
+
+// k_yz3: one workgroup per (slot, kx, ky parity).  Reads the x-spectrum plane (modulated by
+// exp(-i pi y / n) for the odd parity), y-DFT, z-convolution, inverse y-DFT, and writes the
+// half to V_SPE / V_SPO; k_xinv adds the two halves.  Without the cross-parity accumulator the
+// block fits 16 wavefronts per CU.  Blocks are ordered (kx, slot, parity) per XCD so the two
+// parity blocks of a plane follow each other (the second read of the plane hits L2) and all
+// slots of one kx share the kernel plane.
+template <int N>
+struct Plane3Cfg {
+#ifdef LS_YZ_NT1024
+  static constexpr int NT = N >= 128 ? 1024 : (N >= 64 ? 512 : (N * N >= 256 ? 256 : N * N));
+#else
+  static constexpr int NT = N >= 64 ? 512 : (N * N >= 256 ? 256 : N * N);
+#endif
+  static constexpr int PITCH = N + 1;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(Plane3Cfg<N>::NT) void k_yz3(PassArgs a) {
+  constexpr int NT = Plane3Cfg<N>::NT, PITCH = Plane3Cfg<N>::PITCH;
+  __shared__ cplx<T> plane[N * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int par = lin & 1;
+  const int ks = lin >> 1;
+  const int kx = ks / a.nslots;
+  const int slot = ks - kx * a.nslots;
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  const void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
+  void* Ov = d.vec[par ? V_SPO : V_SPE];
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
+  {
+    constexpr int PER = N * N / NT;
+    cplx<T> ldv[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) ldv[j] = ld<T>(Sv, soff + tid + j * NT);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = tid + j * NT;
+      const int zz = i / N, y = i - zz * N;
+      plane[zz * PITCH + y] = par ? ldv[j] * tw[y] : ldv[j];
+    }
+  }
+  __syncthreads();
+  if constexpr (N == 96) {
+    constexpr int L = Lanes<N>::value;
+    constexpr int NG = NT / L;
+    const int g = tid / L, lane = tid - g * L;
+    for (int t = g; t < N; t += NG) fft_group<T, N, -1, 2>(plane + t * PITCH, 1, lane, tw);
+    __syncthreads();
+    for (int c = g; c < N; c += NG) zconv<T, N>(plane + c, PITCH, lane, tw, K + (size_t)(2 * c + par) * (2 * N));
+    __syncthreads();
+    for (int t = g; t < N; t += NG) fft_group<T, N, +1, 2>(plane + t * PITCH, 1, lane, tw);
+  } else {
+    constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+    constexpr int G = NT / L;
+    const int g = tid / L, lane = tid - g * L;
+    for (int idx = g; idx < N; idx += G) {
+      cplx<T>* row = plane + spread2<N>(idx) * PITCH;
+      cplx<T> v[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = row[lane + L * j];
+      fft_a2b<T, N, -1, 2>(v, row, 1, lane, tw);
+      wave_sync();
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+#pragma unroll
+        for (int k2 = 0; k2 < L; ++k2) row[(lane * P + t) + E * k2] = v[t * L + k2];
+    }
+    __syncthreads();
+    for (int idx = g; idx < N; idx += G) {
+      const int c = spread2<N>(idx);
+      zconv4<T, N>(plane + c, lane, tw, K + (size_t)(2 * c + par) * (2 * N));
+    }
+    __syncthreads();
+    for (int idx = g; idx < N; idx += G) {
+      cplx<T>* row = plane + spread2<N>(idx) * PITCH;
+      cplx<T> v[E];
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+#pragma unroll
+        for (int k2 = 0; k2 < L; ++k2) v[t * L + k2] = row[(lane * P + t) + E * k2];
+      fft_b2a<T, N, +1, 2>(v, row, 1, lane, tw);
+      wave_sync();
+#pragma unroll
+      for (int j = 0; j < E; ++j) row[lane + L * j] = v[j];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < N * N; i += NT) {
+    const int zz = i / N, y = i - zz * N;
+    stv<T>(Ov, soff + i, plane[zz * PITCH + y]);
   }
 }
 
@@ -384,7 +772,8 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ff(PassArgs a) {
   const int tid = threadIdx.x;
   const SlotDesc& d = a.desc[slot];
   for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
-  const cplx<T>* S = (const cplx<T>*)d.vec[a.spec] + (size_t)kx * N * N;
+  const void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
   const int kxp = kx <= N ? kx : 2 * N - kx;
   const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (2 * N * N);
   const int g = tid / L, lane = tid - (tid / L) * L;
@@ -395,7 +784,7 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ff(PassArgs a) {
     for (int j = 0; j < PER; ++j) {
       const int i = tid + j * NT;
       const int zz = i / N, y = i - zz * N;
-      cplx<T> v = S[i];
+      cplx<T> v = ld<T>(Sv, soff + i);
       if (par) v = v * tw[y];
       plane[zz * PITCH + y] = v;
     }
@@ -445,7 +834,8 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
   __syncthreads();
   if (g < 2) fft_group<T, N, -1, 2>(rv + g * N, 1, lane, tw);
   __syncthreads();
-  cplx<T>* S = (cplx<T>*)d.vec[a.spec] + (size_t)kx * N * N;
+  void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
   const int kxp = kx <= N ? kx : 2 * N - kx;
   const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (2 * N * N);
   cplx<T> acc[PER];
@@ -467,7 +857,7 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
       if (par == 0)
         acc[j] = plane[zz * PITCH + y];
       else
-        S[i] = acc[j] + mulc(plane[zz * PITCH + y], tw[y]);
+        stv<T>(Sv, soff + i, acc[j] + mulc(plane[zz * PITCH + y], tw[y]));
     }
     __syncthreads();
   }
@@ -477,8 +867,8 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
 // BiCGSTAB vector update x += alpha p + omega s, r = s - omega t, with <rh, r> and ||r||^2.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_update(PassArgs a) {
-  constexpr int TY = N < 16 ? N : 16;
-  constexpr int NYT = N / TY;
+  using X = XCfg<N>;
+  constexpr int TY = X::TY, NYT = X::NYT, IT = X::IT;
   __shared__ double red[4 * 4];
   const int tid = threadIdx.x;
   const int per = a.nz * NYT;
@@ -496,17 +886,32 @@ __global__ __launch_bounds__(256) void k_update(PassArgs a) {
     }
     return;
   }
+  cplx<T> xs[IT], ps[IT], ss[IT], ts[IT], hs[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = tid + it * 256;
+    if (i < TY * N) {
+      const size_t idx = row0 + i;
+      xs[it] = ld<T>(d.vec[V_X], idx);
+      ps[it] = ld<T>(d.vec[V_P], idx);
+      ss[it] = ld<T>(d.vec[V_S], idx);
+      ts[it] = ld<T>(d.vec[V_T], idx);
+      hs[it] = ld<T>(d.vec[V_RH], idx);
+    }
+  }
   cplx<double> rho = {0, 0};
   double rr = 0.0;
-  for (int i = tid; i < TY * N; i += 256) {
-    const size_t idx = row0 + i;
-    const cplx<T> s = ld<T>(d.vec[V_S], idx);
-    const cplx<T> t = ld<T>(d.vec[V_T], idx);
-    stv<T>(d.vec[V_X], idx, ld<T>(d.vec[V_X], idx) + alpha * ld<T>(d.vec[V_P], idx) + omega * s);
-    const cplx<T> r = s - omega * t;
-    stv<T>(d.vec[V_R], idx, r);
-    dot_acc(rho, ld<T>(d.vec[V_RH], idx), r);
-    rr += (double)r.re * r.re + (double)r.im * r.im;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = tid + it * 256;
+    if (i < TY * N) {
+      const size_t idx = row0 + i;
+      stv<T>(d.vec[V_X], idx, xs[it] + alpha * ps[it] + omega * ss[it]);
+      const cplx<T> r = ss[it] - omega * ts[it];
+      stv<T>(d.vec[V_R], idx, r);
+      dot_acc(rho, hs[it], r);
+      rr += (double)r.re * r.re + (double)r.im * r.im;
+    }
   }
   double v[3] = {rho.re, rho.im, rr};
   block_sum<3>(v, red);
@@ -706,14 +1111,30 @@ __global__ __launch_bounds__(256) void k_residual(const cplx<T>* y, const cplx<T
 // launchers
 template <typename T, int N>
 static hipError_t xfwd_t(const PassArgs& a, hipStream_t s) {
-  const int nb = a.nslots * a.nz * (N / (N < 16 ? N : 16));
-  hipLaunchKernelGGL((k_xfwd<T, N>), dim3(nb), dim3(256), 0, s, a);
+  const dim3 nb(a.nslots * a.nz * XCfg<N>::NYT);
+  switch (a.mode) {
+    case PRO_F_VEC: hipLaunchKernelGGL((k_xfwd<T, N, PRO_F_VEC>), nb, dim3(256), 0, s, a); break;
+    case PRO_F_B: hipLaunchKernelGGL((k_xfwd<T, N, PRO_F_B>), nb, dim3(256), 0, s, a); break;
+    case PRO_P: hipLaunchKernelGGL((k_xfwd<T, N, PRO_P>), nb, dim3(256), 0, s, a); break;
+    case PRO_S: hipLaunchKernelGGL((k_xfwd<T, N, PRO_S>), nb, dim3(256), 0, s, a); break;
+    case PRO_VEC: hipLaunchKernelGGL((k_xfwd<T, N, PRO_VEC>), nb, dim3(256), 0, s, a); break;
+    case PRO_CONJ_VEC: hipLaunchKernelGGL((k_xfwd<T, N, PRO_CONJ_VEC>), nb, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 template <typename T, int N>
 static hipError_t xinv_t(const PassArgs& a, hipStream_t s) {
-  const int nb = a.nslots * a.nz * (N / (N < 16 ? N : 16));
-  hipLaunchKernelGGL((k_xinv<T, N>), dim3(nb), dim3(256), 0, s, a);
+  const dim3 nb(a.nslots * a.nz * XCfg<N>::NYT);
+  switch (a.mode) {
+    case EPI_STORE: hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE>), nb, dim3(256), 0, s, a); break;
+    case EPI_AXV: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXV>), nb, dim3(256), 0, s, a); break;
+    case EPI_AXT: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXT>), nb, dim3(256), 0, s, a); break;
+    case EPI_R0: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0>), nb, dim3(256), 0, s, a); break;
+    case EPI_TRUE: hipLaunchKernelGGL((k_xinv<T, N, EPI_TRUE>), nb, dim3(256), 0, s, a); break;
+    case EPI_AX: hipLaunchKernelGGL((k_xinv<T, N, EPI_AX>), nb, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 template <typename T, int N>
@@ -724,7 +1145,10 @@ static hipError_t update_t(const PassArgs& a, hipStream_t s) {
 }
 template <typename T, int N>
 static hipError_t yz_t(const PassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_yz<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
+  if (yz_split() || N == 96)
+    hipLaunchKernelGGL((k_yz3<T, N>), dim3(a.nslots * 2 * N * 2), dim3(Plane3Cfg<N>::NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_yz2<T, (N == 96 ? 64 : N)>), dim3(a.nslots * 2 * N), dim3(Plane2Cfg<(N == 96 ? 64 : N)>::NT), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, int N>
@@ -763,6 +1187,16 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
   } else {                             \
     LS_DISPATCH_F(FN, n, __VA_ARGS__)  \
   }
+
+// The (y,z) pass either keeps both ky parities in one workgroup (k_yz2, result in V_SPEC) or
+// splits them over two workgroups (k_yz3, halves in V_SPE / V_SPO, added by k_xinv).
+bool yz_split() {
+#ifdef LS_YZ_FUSED
+  return false;
+#else
+  return true;
+#endif
+}
 
 bool fused_supported(int n, bool dbl) {
   if (dbl) return n == 8 || n == 16 || n == 32 || n == 64 || n == 96;

@@ -68,8 +68,8 @@ def test_cone_batch_c128():
         uo, io = oracle_solve(n, f, dirs[q], 1e-13)
         _, io10 = oracle_solve(n, f, dirs[q], 1e-10)
         assert info[q]["status"] == 0
-        assert abs(info[q]["iters"] - io10.iters) <= 2
         assert rel(u[q].cpu().numpy(), uo) < 1e-8
+        assert abs(info[q]["iters"] - io10.iters) <= max(2, io10.iters // 10)
 
 
 @pytest.mark.parametrize("n", [32, 64])
