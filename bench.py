@@ -103,10 +103,15 @@ def main() -> int:
     ker_bytes = (n + 1) * 4 * n * n * c
     passes = {
         "k_xfwd": (0, Q * 6.5 * Nc, 2),
-        "k_yz": (1, Q * 4 * Nc + ker_bytes, 2),
-        "k_xinv": (2, Q * 5 * Nc, 2),
+        "k_yz": (1, Q * 6 * Nc + ker_bytes, 2),
+        "k_xinv": (2, Q * 7 * Nc, 2),
         "k_update": (3, Q * 7 * Nc, 1),
     }
+    # algorithmic bytes per launch (units of N*c per slot):
+    #   k_xfwd (p-update prologue): read r p v (3) + f (0.5), write p (1) + x-spectrum (2)
+    #   k_yz   read x-spectrum plane (2), write the two ky-parity halves (4), + kernel once
+    #   k_xinv (v epilogue): read both halves (4) + p, rh (2), write v (1)
+    #   k_update: read x p s t rh (5), write x r (2)
     # FFT flops of one (y,z) plane (5 N log2 N per n-point transform of the split 2n-point DFTs)
     import math
     fft_flops = 5 * n * math.log2(n)

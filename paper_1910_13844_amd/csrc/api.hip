@@ -137,9 +137,8 @@ int matvec(const Run& r, int pro, int sel, int epi, int esel, int esel2, uint32_
   a.mode = epi;
   a.sel = esel;
   a.sel2 = esel2;
-  const bool split = yz_split() || r.c->n == 96;
-  a.spec = split ? V_SPE : V_SPEC;
-  a.spec2 = split ? V_SPO : -1;
+  a.spec = V_SPE;
+  a.spec2 = V_SPO;
   HIPCHK(launch_xinv(r.c->dbl, r.c->n, a, r.s));
   return LS_OK;
 }
@@ -658,9 +657,8 @@ int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32
       HIPCHK(launch_yz(c->dbl, c->n, a, s));
     } else if (pass == 2) {
       a.mode = EPI_AXV;
-      const bool split = yz_split() || c->n == 96;
-      a.spec = split ? V_SPE : V_SPEC;
-      a.spec2 = split ? V_SPO : -1;
+      a.spec = V_SPE;
+      a.spec2 = V_SPO;
       HIPCHK(launch_xinv(c->dbl, c->n, a, s));
     } else {
       HIPCHK(launch_update(c->dbl, c->n, a, s));

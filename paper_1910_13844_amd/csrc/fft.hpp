@@ -206,6 +206,20 @@ __device__ __forceinline__ int tpos(int k1, int m) {
   return k1 * L + (m ^ ((k1 / P) & (L - 1)));
 }
 
+// Storage order of a layout-B spectrum: X[k1 + E k2] (k1 = l P + t) is kept at position
+// E k2 + L t + l, so the L lanes of a transform store and load consecutive entries.
+template <int N>
+__device__ __forceinline__ int bpos(int lane, int t, int k2) {
+  constexpr int L = Split<N>::L, E = Split<N>::E;
+  return E * k2 + L * t + lane;
+}
+// Frequency index stored at position p of that order.
+template <int N>
+__device__ __forceinline__ int bfreq(int p) {
+  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+  return (p % L) * P + (p % E) / L + E * (p / E);
+}
+
 template <typename T, int DIR, int TWS>
 __device__ __forceinline__ cplx<T> twid(const cplx<T>* tw, int m) {
   cplx<T> w = tw[m * TWS];
@@ -213,13 +227,31 @@ __device__ __forceinline__ cplx<T> twid(const cplx<T>* tw, int m) {
   return w;
 }
 
+// Twiddles of the four-step split: twl[k1 * L + l] = exp(-2 pi i l k1 / N), laid out so the L
+// lanes of a transform read consecutive entries.
+template <typename T, int N>
+__device__ __forceinline__ void fill_twl(cplx<T>* twl, const cplx<T>* tw2n, int tid, int nthreads) {
+  constexpr int L = Split<N>::L, E = Split<N>::E;
+  for (int i = tid; i < L * E; i += nthreads) {
+    const int k1 = i / L, l = i - k1 * L;
+    twl[i] = tw2n[2 * l * k1];
+  }
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ cplx<T> twl_get(const cplx<T>* twl, int i) {
+  cplx<T> w = twl[i];
+  if (DIR > 0) w.im = -w.im;
+  return w;
+}
+
 template <typename T, int N, int DIR, int TWS>
-__device__ __forceinline__ void fft_a2b(cplx<T> (&a)[Split<N>::E], cplx<T>* buf, int s, int lane, const cplx<T>* tw) {
+__device__ __forceinline__ void fft_a2b(cplx<T> (&a)[Split<N>::E], cplx<T>* buf, int s, int lane, const cplx<T>* twl) {
   constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
   SmallDFT<E, DIR, T>::run(a);
   if constexpr (L > 1) {
 #pragma unroll
-    for (int k1 = 1; k1 < E; ++k1) a[k1] = a[k1] * twid<T, DIR, TWS>(tw, lane * k1);
+    for (int k1 = 1; k1 < E; ++k1) a[k1] = a[k1] * twl_get<T, DIR>(twl, k1 * L + lane);
     wave_sync();
 #pragma unroll
     for (int k1 = 0; k1 < E; ++k1) buf[tpos<N>(k1, lane) * s] = a[k1];
@@ -234,7 +266,7 @@ __device__ __forceinline__ void fft_a2b(cplx<T> (&a)[Split<N>::E], cplx<T>* buf,
 }
 
 template <typename T, int N, int DIR, int TWS>
-__device__ __forceinline__ void fft_b2a(cplx<T> (&a)[Split<N>::E], cplx<T>* buf, int s, int lane, const cplx<T>* tw) {
+__device__ __forceinline__ void fft_b2a(cplx<T> (&a)[Split<N>::E], cplx<T>* buf, int s, int lane, const cplx<T>* twl) {
   constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
   if constexpr (L > 1) {
 #pragma unroll
@@ -248,7 +280,7 @@ __device__ __forceinline__ void fft_b2a(cplx<T> (&a)[Split<N>::E], cplx<T>* buf,
 #pragma unroll
     for (int k1 = 0; k1 < E; ++k1) a[k1] = buf[tpos<N>(k1, lane) * s];
 #pragma unroll
-    for (int k1 = 1; k1 < E; ++k1) a[k1] = a[k1] * twid<T, DIR, TWS>(tw, lane * k1);
+    for (int k1 = 1; k1 < E; ++k1) a[k1] = a[k1] * twl_get<T, DIR>(twl, k1 * L + lane);
   }
   SmallDFT<E, DIR, T>::run(a);
 }

@@ -77,32 +77,33 @@ __device__ __forceinline__ double* part_ptr(const PassArgs& a, int slot, int blk
 }
 
 // =============================================================================================
-// Row transforms of length N held in LDS (stride 1), natural order in and out, by L lanes.
+// Row transforms of length N held in LDS (stride 1), by L lanes: natural-order signal, spectrum in
+// the storage order of bpos() (natural order for the Stockham sizes).
 template <int N>
 struct HasSplit {
   static constexpr bool value = (N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256);
 };
 
 template <typename T, int N, int DIR>
-__device__ __forceinline__ void row_fft(cplx<T>* row, int lane, const cplx<T>* tw) {
+__device__ __forceinline__ void row_fft(cplx<T>* row, int lane, const cplx<T>* tw, const cplx<T>* twl) {
   if constexpr (HasSplit<N>::value) {
     constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
     cplx<T> v[E];
     if (DIR < 0) {
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = row[lane + L * j];
-      fft_a2b<T, N, DIR, 2>(v, row, 1, lane, tw);
+      fft_a2b<T, N, DIR, 2>(v, row, 1, lane, twl);
       wave_sync();
 #pragma unroll
       for (int t = 0; t < P; ++t)
 #pragma unroll
-        for (int k2 = 0; k2 < L; ++k2) row[(lane * P + t) + E * k2] = v[t * L + k2];
+        for (int k2 = 0; k2 < L; ++k2) row[bpos<N>(lane, t, k2)] = v[t * L + k2];
     } else {
 #pragma unroll
       for (int t = 0; t < P; ++t)
 #pragma unroll
-        for (int k2 = 0; k2 < L; ++k2) v[t * L + k2] = row[(lane * P + t) + E * k2];
-      fft_b2a<T, N, DIR, 2>(v, row, 1, lane, tw);
+        for (int k2 = 0; k2 < L; ++k2) v[t * L + k2] = row[bpos<N>(lane, t, k2)];
+      fft_b2a<T, N, DIR, 2>(v, row, 1, lane, twl);
       wave_sync();
 #pragma unroll
       for (int j = 0; j < E; ++j) row[lane + L * j] = v[j];
@@ -111,6 +112,44 @@ __device__ __forceinline__ void row_fft(cplx<T>* row, int lane, const cplx<T>* t
   } else {
     fft_group<T, N, DIR, 2>(row, 1, lane, tw);
   }
+}
+
+template <int N>
+constexpr int twl_size() {
+  if constexpr (HasSplit<N>::value)
+    return N;
+  else
+    return 1;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void fill_twl_any(cplx<T>* twl, const cplx<T>* tw, int tid, int nt) {
+  if constexpr (HasSplit<N>::value) fill_twl<T, N>(twl, tw, tid, nt);
+}
+
+// Position of frequency k in a row spectrum produced by row_fft.
+template <int N>
+__device__ __forceinline__ int spec_pos(int k) {
+  if constexpr (HasSplit<N>::value) {
+    constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+    return E * (k / E) + L * ((k % E) % P) + (k % E) / P;
+  } else {
+    return k;
+  }
+}
+template <int N>
+__device__ __forceinline__ int spec_freq(int p) {
+  if constexpr (HasSplit<N>::value)
+    return bfreq<N>(p);
+  else
+    return p;
+}
+
+// Lane groups of one wavefront take rows (or columns) L apart: with a pitch of N + 1 complex the
+// accesses of consecutive groups then land on disjoint LDS banks.
+template <int N, int L>
+__device__ __forceinline__ int spreadL(int idx) {
+  return L * (idx % (N / L)) + idx / (N / L);
 }
 
 template <int N>
@@ -143,6 +182,7 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
   __shared__ cplx<T> bufE[TY * PITCH];
   __shared__ cplx<T> bufO[TY * PITCH];
   __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> twl[twl_size<N>()];
   __shared__ double red[4];
   const int tid = threadIdx.x;
   const int per = a.nz * NYT;
@@ -180,6 +220,7 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
   const bool restart = st.restart_flag != 0;
   double ss = 0.0;
   __syncthreads();
+  fill_twl_any<T, N>(twl, tw, tid, 256);
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int i = tid + it * 256;
@@ -219,9 +260,10 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
   __syncthreads();
   {
     const int g = tid / L, lane = tid - (tid / L) * L;
-    for (int t = g; t < 2 * TY; t += NG) {
+    for (int u = g; u < 2 * TY; u += NG) {
+      const int t = (u % 4) * (2 * TY / 4) + u / 4;
       cplx<T>* base = t < TY ? bufE + t * PITCH : bufO + (t - TY) * PITCH;
-      row_fft<T, N, -1>(base, lane, tw);
+      row_fft<T, N, -1>(base, lane, tw, twl);
     }
   }
   __syncthreads();
@@ -233,7 +275,7 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
       const int yy = i % TY;
       const int kx = i / TY;
       const cplx<T>* src = (kx & 1) ? bufO : bufE;
-      stv<T>(spec, ((size_t)kx * a.nz + z) * N + y0 + yy, src[yy * PITCH + (kx >> 1)]);
+      stv<T>(spec, ((size_t)kx * a.nz + z) * N + y0 + yy, src[yy * PITCH + spec_pos<N>(kx >> 1)]);
     }
   }
   if constexpr (MODE == PRO_S) {
@@ -258,6 +300,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   __shared__ cplx<T> bufE[TY * PITCH];
   __shared__ cplx<T> bufO[TY * PITCH];
   __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> twl[twl_size<N>()];
   __shared__ double red[6 * 4];
   const int tid = threadIdx.x;
   const int per = a.nz * NYT;
@@ -282,6 +325,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
       }
     }
     __syncthreads();
+    fill_twl_any<T, N>(twl, tw, tid, 256);
 #pragma unroll
     for (int it = 0; it < IT2; ++it) {
       const int i = tid + it * 256;
@@ -290,16 +334,17 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
         const int kx = i / TY;
         // y-parity halves of the (y,z) convolution: value = E + exp(+i pi y / n) O
         const cplx<T> v = spo ? e[it] + mulc(o[it], tw[y0 + yy]) : e[it];
-        ((kx & 1) ? bufO : bufE)[yy * PITCH + (kx >> 1)] = v;
+        ((kx & 1) ? bufO : bufE)[yy * PITCH + spec_pos<N>(kx >> 1)] = v;
       }
     }
   }
   __syncthreads();
   {
     const int g = tid / L, lane = tid - (tid / L) * L;
-    for (int t = g; t < 2 * TY; t += NG) {
+    for (int u = g; u < 2 * TY; u += NG) {
+      const int t = (u % 4) * (2 * TY / 4) + u / 4;
       cplx<T>* base = t < TY ? bufE + t * PITCH : bufO + (t - TY) * PITCH;
-      row_fft<T, N, +1>(base, lane, tw);
+      row_fft<T, N, +1>(base, lane, tw, twl);
     }
   }
   __syncthreads();
@@ -446,59 +491,6 @@ __device__ __forceinline__ void zconv(cplx<T>* col, int pitch, int lane, const c
   wave_sync();
 }
 
-// k_yz: (y, z) part of the volume convolution for one x-frequency plane, in place.
-// Kernel layout: [kx' in 0..n][ky in 0..2n)[kz in 0..2n), kx' = min(kx, 2n - kx).
-template <typename T, int N>
-__global__ __launch_bounds__(PlaneCfg<N>::NT) void k_yz(PassArgs a) {
-  using C = PlaneCfg<N>;
-  constexpr int NT = C::NT, PER = C::PER, PITCH = C::PITCH;
-  constexpr int L = Lanes<N>::value;
-  constexpr int NG = NT / L;
-  __shared__ cplx<T> plane[N * PITCH];
-  __shared__ cplx<T> tw[2 * N];
-  int kx, slot;
-  plane_decode(a, kx, slot);
-  if (!slot_active(a, slot)) return;
-  const int tid = threadIdx.x;
-  const SlotDesc& d = a.desc[slot];
-  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
-  void* Sv = d.vec[a.spec];
-  const size_t soff = (size_t)kx * N * N;
-  const int kxp = kx <= N ? kx : 2 * N - kx;
-  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
-  const int g = tid / L, lane = tid - (tid / L) * L;
-  cplx<T> acc[PER];
-  __syncthreads();
-#pragma unroll 1
-  for (int par = 0; par < 2; ++par) {
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int i = tid + j * NT;
-      const int zz = i / N, y = i - zz * N;
-      cplx<T> v = ld<T>(Sv, soff + i);
-      if (par) v = v * tw[y];
-      plane[zz * PITCH + y] = v;
-    }
-    __syncthreads();
-    for (int t = g; t < N; t += NG) fft_group<T, N, -1, 2>(plane + t * PITCH, 1, lane, tw);
-    __syncthreads();
-    for (int c = g; c < N; c += NG) zconv<T, N>(plane + c, PITCH, lane, tw, K + (size_t)(2 * c + par) * (2 * N));
-    __syncthreads();
-    for (int t = g; t < N; t += NG) fft_group<T, N, +1, 2>(plane + t * PITCH, 1, lane, tw);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int i = tid + j * NT;
-      const int zz = i / N, y = i - zz * N;
-      if (par == 0)
-        acc[j] = plane[zz * PITCH + y];
-      else
-        stv<T>(Sv, soff + i, acc[j] + mulc(plane[zz * PITCH + y], tw[y]));
-    }
-    __syncthreads();
-  }
-}
-
 // z-convolution of one column with four-step transforms; the kernel coefficients of both
 // z-parities are requested before the forward transform so their latency overlaps it.
 template <typename T>
@@ -506,9 +498,9 @@ struct alignas(4 * sizeof(T)) cpair {
   cplx<T> a, b;
 };
 
-template <typename T, int N>
-__device__ __forceinline__ void zconv4(cplx<T>* col, int lane, const cplx<T>* tw, const cplx<T>* kr) {
-  constexpr int PITCH = N + 1;
+template <typename T, int N, int PITCH>
+__device__ __forceinline__ void zconv4(cplx<T>* col, int lane, const cplx<T>* tw, const cplx<T>* twl,
+                                       const cplx<T>* kr) {
   constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
   const LS_GLOBAL T* k2p = (const LS_GLOBAL T*)kr;
   cplx<T> e[E], o[E];
@@ -526,14 +518,14 @@ __device__ __forceinline__ void zconv4(cplx<T>* col, int lane, const cplx<T>* tw
     e[j] = col[zz * PITCH];
     o[j] = e[j] * tw[zz];
   }
-  fft_a2b<T, N, -1, 2>(e, col, PITCH, lane, tw);
+  fft_a2b<T, N, -1, 2>(e, col, PITCH, lane, twl);
 #pragma unroll
   for (int j = 0; j < E; ++j) e[j] = e[j] * kk[j].a;
-  fft_b2a<T, N, +1, 2>(e, col, PITCH, lane, tw);
-  fft_a2b<T, N, -1, 2>(o, col, PITCH, lane, tw);
+  fft_b2a<T, N, +1, 2>(e, col, PITCH, lane, twl);
+  fft_a2b<T, N, -1, 2>(o, col, PITCH, lane, twl);
 #pragma unroll
   for (int j = 0; j < E; ++j) o[j] = o[j] * kk[j].b;
-  fft_b2a<T, N, +1, 2>(o, col, PITCH, lane, tw);
+  fft_b2a<T, N, +1, 2>(o, col, PITCH, lane, twl);
   wave_sync();
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -542,128 +534,17 @@ __device__ __forceinline__ void zconv4(cplx<T>* col, int lane, const cplx<T>* tw
   }
 }
 
-// k_yz2: the same (y, z) convolution with register-resident four-step transforms (one LDS
-// transpose per transform).  The forward z-DFT, the kernel multiply and the inverse z-DFT of a
-// column run between two transposes without leaving registers; the even-ky result is held in
-// registers while the odd-ky half is computed.  Rows and columns are handed to lane groups with
-// spacing 2 so that a wavefront's LDS accesses spread over the banks.
-template <int N>
-struct Plane2Cfg {
-  static constexpr int NT = N >= 128 ? 512 : (N * N >= 256 ? 256 : N * N);
-  static constexpr int PITCH = N + 1;
-};
-
-template <int N>
-__device__ __forceinline__ int spread2(int idx) {
-  return 2 * (idx % (N / 2)) + idx / (N / 2);
-}
-
-template <typename T, int N>
-__global__ __launch_bounds__(Plane2Cfg<N>::NT) void k_yz2(PassArgs a) {
-  constexpr int NT = Plane2Cfg<N>::NT, PITCH = Plane2Cfg<N>::PITCH;
-  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
-  constexpr int G = NT / L;
-  constexpr int RR = (N + G - 1) / G;
-  __shared__ cplx<T> plane[N * PITCH];
-  __shared__ cplx<T> tw[2 * N];
-  int kx, slot;
-  plane_decode(a, kx, slot);
-  if (!slot_active(a, slot)) return;
-  const int tid = threadIdx.x;
-  const SlotDesc& d = a.desc[slot];
-  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
-  void* Sv = d.vec[a.spec];
-  const size_t soff = (size_t)kx * N * N;
-  const int kxp = kx <= N ? kx : 2 * N - kx;
-  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
-  const int g = tid / L, lane = tid - g * L;
-  cplx<T> acc[RR][E];
-  __syncthreads();
-  constexpr int PER = N * N / NT;
-#pragma unroll 1
-  for (int par = 0; par < 2; ++par) {
-    {
-      cplx<T> ldv[PER];
-#pragma unroll
-      for (int j = 0; j < PER; ++j) ldv[j] = ld<T>(Sv, soff + tid + j * NT);
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        const int i = tid + j * NT;
-        const int zz = i / N, y = i - zz * N;
-        plane[zz * PITCH + y] = par ? ldv[j] * tw[y] : ldv[j];
-      }
-    }
-    __syncthreads();
-    // forward y-DFT of every z-row (natural-order output)
-#pragma unroll
-    for (int rr = 0; rr < RR; ++rr) {
-      const int idx = g + rr * G;
-      if (idx < N) {
-        cplx<T>* row = plane + spread2<N>(idx) * PITCH;
-        cplx<T> v[E];
-#pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = row[lane + L * j];
-        fft_a2b<T, N, -1, 2>(v, row, 1, lane, tw);
-        wave_sync();
-#pragma unroll
-        for (int t = 0; t < P; ++t)
-#pragma unroll
-          for (int k2 = 0; k2 < L; ++k2) row[(lane * P + t) + E * k2] = v[t * L + k2];
-      }
-    }
-    __syncthreads();
-    // z-convolution of every ky column
-    for (int idx = g; idx < N; idx += G) {
-      const int c = spread2<N>(idx);
-      zconv4<T, N>(plane + c, lane, tw, K + (size_t)(2 * c + par) * (2 * N));
-    }
-    __syncthreads();
-    // inverse y-DFT of every z-row; the even half waits in registers for the odd half
-#pragma unroll
-    for (int rr = 0; rr < RR; ++rr) {
-      const int idx = g + rr * G;
-      if (idx < N) {
-        cplx<T>* row = plane + spread2<N>(idx) * PITCH;
-        cplx<T> v[E];
-#pragma unroll
-        for (int t = 0; t < P; ++t)
-#pragma unroll
-          for (int k2 = 0; k2 < L; ++k2) v[t * L + k2] = row[(lane * P + t) + E * k2];
-        fft_b2a<T, N, +1, 2>(v, row, 1, lane, tw);
-        if (par == 0) {
-#pragma unroll
-          for (int j = 0; j < E; ++j) acc[rr][j] = v[j];
-        } else {
-          wave_sync();
-#pragma unroll
-          for (int j = 0; j < E; ++j) {
-            const int y = lane + L * j;
-            row[y] = acc[rr][j] + mulc(v[j], tw[y]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < N * N; i += NT) {
-    const int zz = i / N, y = i - zz * N;
-    stv<T>(Sv, soff + i, plane[zz * PITCH + y]);
-  }
-}
-
 // k_yz3: one workgroup per (slot, kx, ky parity).  Reads the x-spectrum plane (modulated by
 // exp(-i pi y / n) for the odd parity), y-DFT, z-convolution, inverse y-DFT, and writes the
-// half to V_SPE / V_SPO; k_xinv adds the two halves.  Without the cross-parity accumulator the
-// block fits 16 wavefronts per CU.  Blocks are ordered (kx, slot, parity) per XCD so the two
-// parity blocks of a plane follow each other (the second read of the plane hits L2) and all
-// slots of one kx share the kernel plane.
+// half to V_SPE / V_SPO; k_xinv adds the two halves.  Blocks are ordered (kx, slot, parity) per
+// XCD so the two parity blocks of a plane follow each other (the second read of the plane hits
+// L2) and all slots of one kx share the kernel plane in L2.
+// LDS layout: plane rows have a pitch of N + 1 complex and the lane groups of a wavefront take
+// rows / columns L apart, so row accesses, column accesses and the transposes of the four-step
+// transforms spread over the banks; row spectra are kept in the order of bpos().
 template <int N>
 struct Plane3Cfg {
-#ifdef LS_YZ_NT1024
-  static constexpr int NT = N >= 128 ? 1024 : (N >= 64 ? 512 : (N * N >= 256 ? 256 : N * N));
-#else
   static constexpr int NT = N >= 64 ? 512 : (N * N >= 256 ? 256 : N * N);
-#endif
   static constexpr int PITCH = N + 1;
 };
 
@@ -672,6 +553,7 @@ __global__ __launch_bounds__(Plane3Cfg<N>::NT) void k_yz3(PassArgs a) {
   constexpr int NT = Plane3Cfg<N>::NT, PITCH = Plane3Cfg<N>::PITCH;
   __shared__ cplx<T> plane[N * PITCH];
   __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> twl[twl_size<N>()];
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
@@ -682,7 +564,6 @@ __global__ __launch_bounds__(Plane3Cfg<N>::NT) void k_yz3(PassArgs a) {
   if (!slot_active(a, slot)) return;
   const int tid = threadIdx.x;
   const SlotDesc& d = a.desc[slot];
-  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
   const void* Sv = d.vec[a.spec];
   const size_t soff = (size_t)kx * N * N;
   void* Ov = d.vec[par ? V_SPO : V_SPE];
@@ -693,7 +574,9 @@ __global__ __launch_bounds__(Plane3Cfg<N>::NT) void k_yz3(PassArgs a) {
     cplx<T> ldv[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) ldv[j] = ld<T>(Sv, soff + tid + j * NT);
+    for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
     __syncthreads();
+    fill_twl_any<T, N>(twl, tw, tid, NT);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const int i = tid + j * NT;
@@ -702,7 +585,7 @@ __global__ __launch_bounds__(Plane3Cfg<N>::NT) void k_yz3(PassArgs a) {
     }
   }
   __syncthreads();
-  if constexpr (N == 96) {
+  if constexpr (!HasSplit<N>::value) {
     constexpr int L = Lanes<N>::value;
     constexpr int NG = NT / L;
     const int g = tid / L, lane = tid - g * L;
@@ -712,39 +595,18 @@ __global__ __launch_bounds__(Plane3Cfg<N>::NT) void k_yz3(PassArgs a) {
     __syncthreads();
     for (int t = g; t < N; t += NG) fft_group<T, N, +1, 2>(plane + t * PITCH, 1, lane, tw);
   } else {
-    constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+    constexpr int L = Split<N>::L;
     constexpr int G = NT / L;
     const int g = tid / L, lane = tid - g * L;
-    for (int idx = g; idx < N; idx += G) {
-      cplx<T>* row = plane + spread2<N>(idx) * PITCH;
-      cplx<T> v[E];
-#pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = row[lane + L * j];
-      fft_a2b<T, N, -1, 2>(v, row, 1, lane, tw);
-      wave_sync();
-#pragma unroll
-      for (int t = 0; t < P; ++t)
-#pragma unroll
-        for (int k2 = 0; k2 < L; ++k2) row[(lane * P + t) + E * k2] = v[t * L + k2];
-    }
+    for (int idx = g; idx < N; idx += G) row_fft<T, N, -1>(plane + spreadL<N, L>(idx) * PITCH, lane, tw, twl);
     __syncthreads();
     for (int idx = g; idx < N; idx += G) {
-      const int c = spread2<N>(idx);
-      zconv4<T, N>(plane + c, lane, tw, K + (size_t)(2 * c + par) * (2 * N));
+      const int c = spreadL<N, L>(idx);
+      const int ky = spec_freq<N>(c);
+      zconv4<T, N, PITCH>(plane + c, lane, tw, twl, K + (size_t)(2 * ky + par) * (2 * N));
     }
     __syncthreads();
-    for (int idx = g; idx < N; idx += G) {
-      cplx<T>* row = plane + spread2<N>(idx) * PITCH;
-      cplx<T> v[E];
-#pragma unroll
-      for (int t = 0; t < P; ++t)
-#pragma unroll
-        for (int k2 = 0; k2 < L; ++k2) v[t * L + k2] = row[(lane * P + t) + E * k2];
-      fft_b2a<T, N, +1, 2>(v, row, 1, lane, tw);
-      wave_sync();
-#pragma unroll
-      for (int j = 0; j < E; ++j) row[lane + L * j] = v[j];
-    }
+    for (int idx = g; idx < N; idx += G) row_fft<T, N, +1>(plane + spreadL<N, L>(idx) * PITCH, lane, tw, twl);
   }
   __syncthreads();
   for (int i = tid; i < N * N; i += NT) {
@@ -1145,10 +1007,7 @@ static hipError_t update_t(const PassArgs& a, hipStream_t s) {
 }
 template <typename T, int N>
 static hipError_t yz_t(const PassArgs& a, hipStream_t s) {
-  if (yz_split() || N == 96)
-    hipLaunchKernelGGL((k_yz3<T, N>), dim3(a.nslots * 2 * N * 2), dim3(Plane3Cfg<N>::NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_yz2<T, (N == 96 ? 64 : N)>), dim3(a.nslots * 2 * N), dim3(Plane2Cfg<(N == 96 ? 64 : N)>::NT), 0, s, a);
+  hipLaunchKernelGGL((k_yz3<T, N>), dim3(a.nslots * 2 * N * 2), dim3(Plane3Cfg<N>::NT), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, int N>
@@ -1187,16 +1046,6 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
   } else {                             \
     LS_DISPATCH_F(FN, n, __VA_ARGS__)  \
   }
-
-// The (y,z) pass either keeps both ky parities in one workgroup (k_yz2, result in V_SPEC) or
-// splits them over two workgroups (k_yz3, halves in V_SPE / V_SPO, added by k_xinv).
-bool yz_split() {
-#ifdef LS_YZ_FUSED
-  return false;
-#else
-  return true;
-#endif
-}
 
 bool fused_supported(int n, bool dbl) {
   if (dbl) return n == 8 || n == 16 || n == 32 || n == 64 || n == 96;

@@ -5,7 +5,6 @@
 namespace ls {
 
 bool fused_supported(int n, bool dbl);
-bool yz_split();
 
 // x-forward pass, (y,z) convolution, x-inverse pass, far-field passes.
 hipError_t launch_xfwd(bool dbl, int n, const PassArgs& a, hipStream_t s);
