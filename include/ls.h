@@ -135,6 +135,20 @@ int ls_vjp(const ls_ctx* ctx, const void* f, const void* u, int32_t Q, const voi
 int ls_grad(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, const void* y_meas, void* grad,
             double* loss, const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* Building blocks of the gradient for callers that schedule the solves themselves (the
+ * continuous-batching loop):
+ *   ls_residual: r_q = y_q - y_meas,q and FP64 sums stats[2q] = ||r_q||^2, stats[2q+1] = ||y_meas,q||^2
+ *     (the data term of eq. (prob) is sum_q stats[2q] / (2 stats[2q+1])).  y, y_meas, r: [Q][m][m]
+ *     device (r may alias y); stats: [2Q] device doubles.
+ *   ls_grad_accumulate: grad[i] (+)= sum_q w_q Re(u_q[i] wb_q[i]) (Algorithm 1, gradient step, with
+ *     wb_q solving (I - G diag f) wb_q = G~^T conj(r_q)); w_q = 1 / stats[2q+1] when stats is given,
+ *     else 1.  Summed over q in index order in FP64.  u, wb: [Q][N]; grad: [N] real, overwritten when
+ *     accumulate == 0, added to otherwise. */
+int ls_residual(const ls_ctx* ctx, const void* y, const void* y_meas, int32_t Q, void* r, double* stats,
+                void* stream);
+int ls_grad_accumulate(const ls_ctx* ctx, const void* u, const void* wb, int32_t Q, const double* stats,
+                       void* grad, int32_t accumulate, void* stream);
+
 /* Continuous batching (slot pool).  A batch holds `nslots` independent solves of eq. (lipp1) on
  * one context (one grid size); each slot has its own potential, right-hand side and output.
  * Slots are admitted and harvested between steps while the others keep iterating, so requests

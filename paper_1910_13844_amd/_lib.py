@@ -21,6 +21,7 @@ EXPORTS = [
     "ls_ctx_destroy", "ls_workspace_bytes", "ls_apply_G", "ls_apply_A", "ls_forward", "ls_farfield",
     "ls_farfield_adj", "ls_vjp", "ls_grad", "ls_batch_bytes", "ls_batch_create", "ls_batch_admit",
     "ls_batch_step", "ls_batch_poll", "ls_batch_release", "ls_batch_destroy", "ls_profile_pass",
+    "ls_residual", "ls_grad_accumulate",
 ]
 
 
@@ -81,6 +82,8 @@ def load() -> C.CDLL:
         "ls_batch_release": (C.c_int, [vp, i32]),
         "ls_batch_destroy": (None, [vp]),
         "ls_profile_pass": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, sz, vp]),
+        "ls_residual": (C.c_int, [vp, vp, vp, i32, vp, vp, vp]),
+        "ls_grad_accumulate": (C.c_int, [vp, vp, vp, i32, vp, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

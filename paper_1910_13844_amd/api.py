@@ -182,6 +182,25 @@ class Context:
                                  _stream(stream)), "ls_grad")
         return loss.value, grad, [i.as_dict() for i in info]
 
+    def ls_residual(self, y: torch.Tensor, y_meas: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None
+                    ) -> Tuple[torch.Tensor, torch.Tensor]:
+        """r = y - y_meas and FP64 [||r_q||^2, ||y_meas_q||^2] per illumination."""
+        y, y_meas = y.contiguous(), y_meas.contiguous()
+        Q = y.numel() // (self.n * self.n)
+        r = torch.empty_like(y) if out is None else out
+        stats = torch.empty(2 * Q, dtype=torch.float64, device=self.device)
+        L.check(self.lib.ls_residual(self.h, _ptr(y), _ptr(y_meas), Q, _ptr(r), _ptr(stats), _stream(stream)),
+                "ls_residual")
+        return r, stats
+
+    def ls_grad_accumulate(self, u: torch.Tensor, wb: torch.Tensor, grad: torch.Tensor,
+                           stats: Optional[torch.Tensor] = None, accumulate: bool = False, stream=None) -> torch.Tensor:
+        u, wb = self._chk_vol(u, "u"), self._chk_vol(wb, "wb")
+        Q = u.numel() // self.N
+        L.check(self.lib.ls_grad_accumulate(self.h, _ptr(u), _ptr(wb), Q, _ptr(stats), _ptr(grad),
+                                            int(bool(accumulate)), _stream(stream)), "ls_grad_accumulate")
+        return grad
+
 
 def profile_pass(ctx: "Context", f: torch.Tensor, u: torch.Tensor, pass_id: int, reps: int,
                  ws: torch.Tensor, stream=None) -> None:

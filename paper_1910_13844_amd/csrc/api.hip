@@ -667,6 +667,20 @@ int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32
   return LS_OK;
 }
 
+int ls_residual(const ls_ctx* c, const void* y, const void* y_meas, int32_t Q, void* r, double* stats,
+                void* stream) {
+  if (check_ctx(c) || !y || !y_meas || !r || !stats || Q < 1) return LS_ERR_ARG;
+  HIPCHK(launch_residual(c->dbl, c->n, y, y_meas, Q, r, stats, (hipStream_t)stream));
+  return LS_OK;
+}
+
+int ls_grad_accumulate(const ls_ctx* c, const void* u, const void* wb, int32_t Q, const double* stats, void* grad,
+                       int32_t accumulate, void* stream) {
+  if (check_ctx(c) || !u || !wb || !grad || Q < 1) return LS_ERR_ARG;
+  HIPCHK(launch_grad_sum(c->dbl, u, wb, Q, c->N, stats, grad, accumulate, (hipStream_t)stream));
+  return LS_OK;
+}
+
 }  // extern "C"
 
 // =============================================================================================

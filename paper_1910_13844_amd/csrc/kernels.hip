@@ -941,6 +941,21 @@ __global__ __launch_bounds__(256) void k_grad_accum(const SlotDesc* desc, const 
   grad[i] = s;
 }
 
+// grad[i] (+)= sum_q w_q Re(u_q[i] wb_q[i]) over contiguous [Q][N] arrays, FP64 sum in q order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_sum(const cplx<T>* u, const cplx<T>* wb, int Q, size_t N,
+                                                  const double* stats, T* grad, int accumulate) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double s = accumulate ? (double)grad[i] : 0.0;
+  for (int q = 0; q < Q; ++q) {
+    const cplx<T> a = u[(size_t)q * N + i], b = wb[(size_t)q * N + i];
+    const double wq = stats ? 1.0 / stats[2 * q + 1] : 1.0;
+    s += wq * ((double)a.re * b.re - (double)a.im * b.im);
+  }
+  grad[i] = (T)s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_convert(const double* src, T* dst, size_t N) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -1082,6 +1097,18 @@ hipError_t launch_grad_accum(bool dbl, int n, const SlotDesc* desc, const double
   else
     hipLaunchKernelGGL(k_grad_accum<float>, dim3(nb), dim3(256), 0, s, desc, w, nslots, sel_u, sel_w, (double*)grad,
                        N, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_sum(bool dbl, const void* u, const void* wb, int Q, size_t N, const double* stats, void* grad,
+                           int accumulate, hipStream_t s) {
+  const int nb = (int)((N + 255) / 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_grad_sum<double>, dim3(nb), dim3(256), 0, s, (const cplx<double>*)u,
+                       (const cplx<double>*)wb, Q, N, stats, (double*)grad, accumulate);
+  else
+    hipLaunchKernelGGL(k_grad_sum<float>, dim3(nb), dim3(256), 0, s, (const cplx<float>*)u, (const cplx<float>*)wb,
+                       Q, N, stats, (float*)grad, accumulate);
   return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ hipError_t launch_scalar(int kind, bool dbl, const PassArgs& a, hipStream_t s);
 // gradient helpers
 hipError_t launch_grad_accum(bool dbl, int n, const SlotDesc* desc, const double* w, int nslots, int sel_u,
                              int sel_w, void* grad, int accumulate, hipStream_t s);
+hipError_t launch_grad_sum(bool dbl, const void* u, const void* wb, int Q, size_t N, const double* stats, void* grad,
+                           int accumulate, hipStream_t s);
 hipError_t launch_convert(bool dbl, const double* src, void* dst, size_t N, hipStream_t s);
 hipError_t launch_residual(bool dbl, int m, const void* y, const void* ymeas, int Q, void* r, double* stats,
                            hipStream_t s);

@@ -1,0 +1,333 @@
+"""Continuous-batching request loop over the slot API (ls_batch_*).
+
+Requests (forward or gradient, any supported grid size, 1..Q illuminations each) arrive over time.
+Each illumination solve becomes a job; one slot pool per grid size keeps the Krylov state and the
+Green kernels of that size resident on the device.  Between BiCGSTAB steps the loop harvests
+finished slots and admits waiting jobs into free slots, so work that arrives while other work is on
+the GPU joins the same kernel launches.  A gradient request runs its forward solves, then its far
+field and residual, then one adjoint solve per illumination (right-hand side G~^T conj(r)), then the
+gradient accumulation.  Each result is the same alone and in a mix: slots never interact (per-slot
+reductions in a fixed order).
+
+Engines: ``GpuEngine`` drives libls through ``api``; tests substitute a CPU engine with the same
+methods to exercise the scheduler without a GPU.
+
+    python -m paper_1910_13844_amd.serve --requests 40 --rate 20 --grids 64,96,128
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import sys
+import time
+from collections import deque
+from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str            # "forward" or "grad"
+    n: int
+    Q: int
+    arrival: float       # seconds from the start of the trace
+    seed: int
+    theta: float
+    # filled by the loop
+    done_time: Optional[float] = None
+    outputs: dict = dataclasses.field(default_factory=dict)
+
+
+@dataclasses.dataclass
+class Job:
+    req: Request
+    q: int
+    phase: str           # "fwd" or "adj"
+    slot: int = -1
+
+
+def poisson_trace(nreq: int, rate: float, grids: Sequence[int], qmax: int = 60, seed: int = 6,
+                  grad_fraction: float = 0.5) -> List[Request]:
+    """Poisson arrivals (exponential gaps, mean 1/rate), kind forward/gradient with equal odds,
+    grid uniform over `grids`, illuminations uniform over 1..qmax; phantom seed = request id."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(nreq):
+        t += rng.exponential(1.0 / rate)
+        kind = "grad" if rng.uniform() < grad_fraction else "forward"
+        n = int(rng.choice(list(grids)))
+        Q = int(rng.integers(1, qmax + 1))
+        out.append(Request(i, kind, n, Q, t, seed=i, theta=40.0 if kind == "grad" else 45.0))
+    return out
+
+
+class Scheduler:
+    """Continuous batching over per-grid-size slot pools.
+
+    engine: object with
+      pool_capacity(n) -> int
+      prepare(req)                          -> per-request device data (potential, directions, data)
+      admit(n, slot, job)                   -> start the job's solve in `slot` of pool n
+      step(n, iters)                        -> advance every running slot of pool n
+      poll(n) -> (states, infos)            -> 0 idle, 1 running, 2 done
+      release(n, slot)
+      finish_forward(req)                   -> after all forward solves: far field (and, for
+                                               gradient requests, residual + adjoint right-hand sides)
+      finish_grad(req)                      -> after all adjoint solves: gradient accumulation
+    """
+
+    def __init__(self, engine, iters_per_step: int = 2, clock: Callable[[], float] = time.perf_counter):
+        self.e = engine
+        self.iters = iters_per_step
+        self.clock = clock
+        self.pending: Dict[int, Deque[Job]] = {}
+        self.slots: Dict[int, List[Optional[Job]]] = {}
+        self.left: Dict[Tuple[int, str], int] = {}
+        self.completed: List[Request] = []
+        self.solves = 0
+
+    def _pool(self, n):
+        if n not in self.slots:
+            self.slots[n] = [None] * self.e.pool_capacity(n)
+            self.pending[n] = deque()
+        return self.slots[n]
+
+    def submit(self, req: Request):
+        self._pool(req.n)
+        self.e.prepare(req)
+        self.left[(req.rid, "fwd")] = req.Q
+        for q in range(req.Q):
+            self.pending[req.n].append(Job(req, q, "fwd"))
+
+    def _fill(self, n):
+        slots = self.slots[n]
+        for i, s in enumerate(slots):
+            if s is None and self.pending[n]:
+                job = self.pending[n].popleft()
+                job.slot = i
+                self.e.admit(n, i, job)
+                slots[i] = job
+
+    def _harvest(self, n, t0):
+        states, infos = self.e.poll(n)
+        slots = self.slots[n]
+        for i, job in enumerate(slots):
+            if job is None or states[i] != 2:
+                continue
+            self.e.release(n, i)
+            slots[i] = None
+            self.solves += 1
+            req = job.req
+            req.outputs.setdefault("info_" + job.phase, {})[job.q] = infos[i]
+            key = (req.rid, job.phase)
+            self.left[key] -= 1
+            if self.left[key] == 0:
+                if job.phase == "fwd":
+                    self.e.finish_forward(req)
+                    if req.kind == "grad":
+                        self.left[(req.rid, "adj")] = req.Q
+                        for q in range(req.Q):
+                            self.pending[n].append(Job(req, q, "adj"))
+                    else:
+                        req.done_time = self.clock() - t0
+                        self.completed.append(req)
+                else:
+                    self.e.finish_grad(req)
+                    req.done_time = self.clock() - t0
+                    self.completed.append(req)
+
+    def busy(self) -> bool:
+        return any(s is not None for pool in self.slots.values() for s in pool) or any(self.pending.values())
+
+    def run(self, trace: Sequence[Request], realtime: bool = True) -> dict:
+        trace = sorted(trace, key=lambda r: r.arrival)
+        t0 = self.clock()
+        nxt = 0
+        while nxt < len(trace) or self.busy():
+            now = self.clock() - t0
+            while nxt < len(trace) and (trace[nxt].arrival <= now or not realtime or not self.busy()):
+                if realtime and trace[nxt].arrival > now and not self.busy():
+                    # idle: wait for the next arrival
+                    time.sleep(max(0.0, trace[nxt].arrival - now))
+                self.submit(trace[nxt])
+                nxt += 1
+                now = self.clock() - t0
+            for n in list(self.slots):
+                self._fill(n)
+                if any(s is not None for s in self.slots[n]):
+                    self.e.step(n, self.iters)
+                    self._harvest(n, t0)
+        total = self.clock() - t0
+        return summarize(self.completed, total, self.solves)
+
+
+def summarize(done: Sequence[Request], total: float, solves: int) -> dict:
+    lat = [r.done_time - r.arrival for r in done]
+    return {"requests": len(done), "solves": solves, "seconds": total,
+            "solves_per_s": solves / total if total > 0 else float("nan"),
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)) if lat else None,
+            "p99_ms": 1e3 * float(np.percentile(lat, 99)) if lat else None}
+
+
+# ---------------------------------------------------------------------------------------------
+class GpuEngine:
+    """Scheduler engine backed by libls on one GPU."""
+
+    def __init__(self, hbm_budget_gb: float = 120.0, tol: float = 1e-5, maxit: int = 500, prec: str = "c64",
+                 device: str = "cuda:0", max_slots: int = 64):
+        import torch
+
+        from . import _lib, api, workloads
+
+        self.torch, self.api, self.wl, self._lib = torch, api, workloads, _lib
+        self.tol, self.maxit, self.prec, self.device = tol, maxit, prec, device
+        self.budget = hbm_budget_gb * 1e9
+        self.max_slots = max_slots
+        self.ctx: Dict[int, "api.Context"] = {}
+        self.pool: Dict[int, "api.Batch"] = {}
+        self.data: Dict[int, dict] = {}
+
+    def _ctx(self, n):
+        if n not in self.ctx:
+            self.ctx[n] = self.api.Context(n, self.wl.k_of(), p=4, xg=float(n), prec=self.prec, device=self.device)
+        return self.ctx[n]
+
+    def pool_capacity(self, n):
+        c = self._ctx(n)
+        per_slot = c.workspace_bytes(2, self._lib.LS_OP_FORWARD) - c.workspace_bytes(1, self._lib.LS_OP_FORWARD)
+        share = self.budget / 3.0
+        cap = int(max(1, min(self.max_slots, share // max(per_slot, 1))))
+        self.pool[n] = self.api.Batch(c, cap, tol=self.tol, maxit=self.maxit)
+        return cap
+
+    def preload(self, trace: Sequence[Request]):
+        """Generate every request's inputs before the trace starts (not part of the served work):
+        the potential, the illumination directions and, for gradient requests, synthetic measurements
+        of a perturbed phantom."""
+        torch = self.torch
+        for req in trace:
+            c = self._ctx(req.n)
+            f = self.wl.blob_potential(req.seed, req.n, dn_max=0.05)
+            d = {"f": torch.from_numpy(f).to(self.device, c.rdtype), "dirs": self.wl.cone_dirs(req.Q, req.theta)}
+            if req.kind == "grad":
+                pert = self.wl.blob_potential(req.seed + 100000, req.n, nblobs=5, sigma_range=(2.0, 5.0),
+                                              dn_max=0.01)
+                ft = torch.from_numpy(f + pert).to(self.device, c.rdtype)
+                ut, _ = c.ls_forward(ft, d["dirs"], tol=self.tol)
+                d["y_meas"] = c.ls_farfield(ft, ut)
+                del ut
+            self.data[req.rid] = d
+        torch.cuda.synchronize()
+
+    def prepare(self, req: Request):
+        c = self._ctx(req.n)
+        d = self.data[req.rid]
+        d["u"] = self.torch.empty((req.Q, req.n, req.n, req.n), dtype=c.cdtype, device=self.device)
+        if req.kind == "grad":
+            d["w"] = self.torch.empty_like(d["u"])
+
+    def admit(self, n, slot, job: Job):
+        d = self.data[job.req.rid]
+        if job.phase == "fwd":
+            self.pool[n].ls_batch_admit(slot, d["f"], d["u"][job.q], direction=d["dirs"][job.q])
+        else:
+            self.pool[n].ls_batch_admit(slot, d["f"], d["w"][job.q], rhs=d["b"][job.q])
+
+    def step(self, n, iters):
+        self.pool[n].ls_batch_step(iters)
+
+    def poll(self, n):
+        return self.pool[n].ls_batch_poll()
+
+    def release(self, n, slot):
+        self.pool[n].ls_batch_release(slot)
+
+    def finish_forward(self, req: Request):
+        c = self.ctx[req.n]
+        d = self.data[req.rid]
+        d["y"] = c.ls_farfield(d["f"], d["u"])
+        if req.kind == "grad":
+            r, d["stats"] = c.ls_residual(d["y"], d["y_meas"])
+            st = d["stats"].cpu().numpy()
+            d["loss"] = float(np.sum(st[0::2] / (2.0 * st[1::2])))
+            d["b"] = c.ls_farfield_adj(r, conj=True)
+        else:
+            req.outputs["y"] = d["y"]
+
+    def finish_grad(self, req: Request):
+        d = self.data[req.rid]
+        c = self.ctx[req.n]
+        g = self.torch.empty((req.n,) * 3, dtype=c.rdtype, device=self.device)
+        req.outputs["grad"] = c.ls_grad_accumulate(d["u"], d["w"], g, stats=d["stats"])
+        req.outputs["loss"] = d["loss"]
+        self.data.pop(req.rid, None)
+
+
+def one_at_a_time(engine_factory, trace: Sequence[Request]) -> dict:
+    """Baseline: requests served in arrival order, each illumination solved alone (Q = 1 calls)."""
+    import torch
+
+    e = engine_factory()
+    e.preload(trace)
+    t0 = time.perf_counter()
+    solves = 0
+    done = []
+    for req in sorted(trace, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if req.arrival > now:
+            time.sleep(req.arrival - now)
+        e.prepare(req)
+        c = e._ctx(req.n)
+        d = e.data[req.rid]
+        for q in range(req.Q):
+            c.ls_forward(d["f"], d["dirs"][q:q + 1], tol=e.tol, u=d["u"][q:q + 1])
+            solves += 1
+        if req.kind == "grad":
+            e.finish_forward(req)
+            bt = e.api.Batch(c, 1, tol=e.tol, maxit=e.maxit)
+            for q in range(req.Q):
+                # adjoint solve for one illumination (stored right-hand side) through a one-slot pool
+                bt.ls_batch_admit(0, d["f"], d["w"][q], rhs=d["b"][q])
+                while bt.ls_batch_poll()[0][0] != 2:
+                    bt.ls_batch_step(2)
+                bt.ls_batch_release(0)
+                solves += 1
+            e.finish_grad(req)
+        else:
+            e.finish_forward(req)
+        req.done_time = time.perf_counter() - t0
+        done.append(req)
+    torch.cuda.synchronize()
+    return summarize(done, time.perf_counter() - t0, solves)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=40)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--grids", default="64,96,128")
+    ap.add_argument("--qmax", type=int, default=60)
+    ap.add_argument("--budget-gb", type=float, default=120.0)
+    ap.add_argument("--baseline", action="store_true", help="also run the one-solve-at-a-time baseline")
+    args = ap.parse_args(argv)
+    grids = [int(g) for g in args.grids.split(",")]
+    mk = lambda: poisson_trace(args.requests, args.rate, grids, args.qmax)  # noqa: E731
+    eng = GpuEngine(hbm_budget_gb=args.budget_gb)
+    trace = mk()
+    eng.preload(trace)
+    sched = Scheduler(eng)
+    res = {"continuous": sched.run(trace)}
+    if args.baseline:
+        res["one_at_a_time"] = one_at_a_time(lambda: GpuEngine(hbm_budget_gb=args.budget_gb), mk())
+    res["config"] = {"requests": args.requests, "rate": args.rate, "grids": grids, "qmax": args.qmax}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
