@@ -43,7 +43,7 @@ extern "C" {
 
 /* Geometry of one problem (Theorem 1, Proposition 2, Section on G~). */
 typedef struct {
-  int32_t n;    /* voxels per side; supported: 8, 16, 32, 64, 96, 128 (LS_C64), up to 96 (LS_C128) */
+  int32_t n;    /* voxels per side; supported: 8, 16, 32, 64, 96, 128, 192, 256 (both precisions) */
   int32_t p;    /* Theorem 1 padding factor, even, >= 2 (p = 4 recommended); only the 2n grid is stored */
   double kbh;   /* k_b h; must satisfy 0 < kbh < pi (Nyquist condition of Theorem 1) */
   double xg;    /* detector plane position x_Gamma / h; must exceed n/2 (plane outside Omega) */

@@ -127,6 +127,17 @@ struct Run {
   }
 };
 
+// Where k_xinv finds the output of the (y,z) pass.
+void xinv_source(const ls_ctx* c, PassArgs& a) {
+  if (plane_split(c->n, c->dbl)) {
+    a.spec = V_SPEC;
+    a.spec2 = -1;
+  } else {
+    a.spec = V_SPE;
+    a.spec2 = V_SPO;
+  }
+}
+
 int matvec(const Run& r, int pro, int sel, int epi, int esel, int esel2, uint32_t mask) {
   PassArgs a = r.base();
   a.mask = mask;
@@ -137,8 +148,7 @@ int matvec(const Run& r, int pro, int sel, int epi, int esel, int esel2, uint32_
   a.mode = epi;
   a.sel = esel;
   a.sel2 = esel2;
-  a.spec = V_SPE;
-  a.spec2 = V_SPO;
+  xinv_source(r.c, a);
   HIPCHK(launch_xinv(r.c->dbl, r.c->n, a, r.s));
   return LS_OK;
 }
@@ -657,8 +667,7 @@ int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32
       HIPCHK(launch_yz(c->dbl, c->n, a, s));
     } else if (pass == 2) {
       a.mode = EPI_AXV;
-      a.spec = V_SPE;
-      a.spec2 = V_SPO;
+      xinv_source(c, a);
       HIPCHK(launch_xinv(c->dbl, c->n, a, s));
     } else {
       HIPCHK(launch_update(c->dbl, c->n, a, s));

@@ -84,7 +84,7 @@ struct HasSplit {
   static constexpr bool value = (N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256);
 };
 
-template <typename T, int N, int DIR>
+template <typename T, int N, int DIR, int TWS = 2>
 __device__ __forceinline__ void row_fft(cplx<T>* row, int lane, const cplx<T>* tw, const cplx<T>* twl) {
   if constexpr (HasSplit<N>::value) {
     constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void row_fft(cplx<T>* row, int lane, const cplx<T>* t
     }
     wave_sync();
   } else {
-    fft_group<T, N, DIR, 2>(row, 1, lane, tw);
+    fft_group<T, N, DIR, TWS>(row, 1, lane, tw);
   }
 }
 
@@ -726,6 +726,260 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
 }
 
 // =============================================================================================
+// Grid sizes whose n x n plane does not fit in LDS (complex64 n = 192, 256; complex128 n = 128).
+// The (y,z) pass is split in two kernels around a [kx][ky][z] spectrum:
+//   k_yzA  one workgroup per (slot, kx, ky class c): the zero-padded 2n-point y-DFT restricted to
+//          ky = c (mod C) is an M-point DFT (M = 2n / C) of the row folded with exp(-i pi c y / n);
+//          each of the M ky columns is z-convolved with the kernel; written as [kx][ky][z].
+//   k_yzB  one workgroup per (slot, kx, tile of 16 z): cropped inverse 2n-point y-DFT (even and odd
+//          ky halves, as in k_xinv) and written back as [kx][z][y], which k_xinv reads as usual.
+// M: ky columns per class, the largest supported transform length for which the N x M slab
+// (pitch M + 1) fits in LDS.
+template <typename T, int N>
+constexpr int big_m() {
+  if constexpr (sizeof(T) == 4)
+    return N == 192 ? 96 : 64;
+  else
+    return N == 128 ? 64 : 32;
+}
+
+template <typename T, int N>
+struct BigCfg {
+  static constexpr int M = big_m<T, N>();
+  static constexpr int C = 2 * N / M;
+  static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
+  static constexpr int PITCH = M + 1;
+  static_assert(N % M == 0, "fold needs n / M integral");
+};
+
+template <typename T, int M, int TWS>
+__device__ __forceinline__ void fill_twl_stride(cplx<T>* twl, const cplx<T>* tw, int tid, int nt) {
+  // twl[k1 * L + l] = exp(-2 pi i l k1 / M) from a table of exp(-2 pi i m / (M TWS))
+  if constexpr (HasSplit<M>::value) {
+    constexpr int L = Split<M>::L, E = Split<M>::E;
+    for (int i = tid; i < L * E; i += nt) {
+      const int k1 = i / L, l = i - k1 * L;
+      twl[i] = tw[TWS * l * k1];
+    }
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((BigCfg<T, N>::NT)) void k_yzA(PassArgs a) {
+  using B = BigCfg<T, N>;
+  constexpr int C = B::C, M = B::M, NT = B::NT, PITCH = B::PITCH, F = N / M;
+  __shared__ cplx<T> plane[N * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> twlM[twl_size<M>()];
+  __shared__ cplx<T> twlN[twl_size<N>()];
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int c = lin % C;
+  const int ks = lin / C;
+  const int kx = ks / a.nslots;
+  const int slot = ks - kx * a.nslots;
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  const void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
+  __syncthreads();
+  fill_twl_stride<T, M, C>(twlM, tw, tid, NT);
+  fill_twl_any<T, N>(twlN, tw, tid, NT);
+  // fold the zero-padded row onto M points: z_c[j] = sum_m x[j + m M] exp(-i pi c (j + m M) / n)
+  for (int idx = tid; idx < N * M; idx += NT) {
+    const int zz = idx / M, j = idx - zz * M;
+    cplx<T> acc = {0, 0};
+#pragma unroll
+    for (int m = 0; m < F; ++m) {
+      const int y = j + m * M;
+      acc = acc + ld<T>(Sv, soff + (size_t)zz * N + y) * tw[(c * y) % (2 * N)];
+    }
+    plane[zz * PITCH + j] = acc;
+  }
+  __syncthreads();
+  {
+    constexpr int LM = row_lanes<M>();
+    constexpr int G = NT / LM;
+    const int g = tid / LM, lane = tid - g * LM;
+    for (int r = g; r < N; r += G) row_fft<T, M, -1, C>(plane + r * PITCH, lane, tw, twlM);
+  }
+  __syncthreads();
+  if constexpr (HasSplit<N>::value) {
+    constexpr int L = Split<N>::L;
+    constexpr int G = NT / L;
+    const int g = tid / L, lane = tid - g * L;
+    for (int j = g; j < M; j += G) {
+      const int ky = c + C * spec_freq<M>(j);
+      zconv4<T, N, PITCH>(plane + j, lane, tw, twlN, K + (size_t)ky * (2 * N));
+    }
+  } else {
+    constexpr int L = Lanes<N>::value;
+    constexpr int G = NT / L;
+    const int g = tid / L, lane = tid - g * L;
+    for (int j = g; j < M; j += G) {
+      const int ky = c + C * spec_freq<M>(j);
+      zconv<T, N>(plane + j, PITCH, lane, tw, K + (size_t)ky * (2 * N));
+    }
+  }
+  __syncthreads();
+  void* S2 = d.vec[V_SPE];
+  for (int idx = tid; idx < N * M; idx += NT) {
+    const int j = idx / N, zz = idx - j * N;
+    const int ky = c + C * spec_freq<M>(j);
+    stv<T>(S2, ((size_t)kx * 2 * N + ky) * N + zz, plane[zz * PITCH + j]);
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_yzB(PassArgs a) {
+  constexpr int TZ = 16, PITCH = N + 1;
+  constexpr int L = row_lanes<N>();
+  constexpr int NG = 256 / L;
+  __shared__ cplx<T> bE[TZ * PITCH];
+  __shared__ cplx<T> bO[TZ * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> twl[twl_size<N>()];
+  const int per = 2 * N * (N / TZ);
+  const int slot = blockIdx.x / per;
+  const int rem = blockIdx.x - slot * per;
+  const int kx = rem / (N / TZ);
+  const int z0 = (rem - kx * (N / TZ)) * TZ;
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
+  const void* S2 = d.vec[V_SPE];
+  for (int idx = tid; idx < 2 * N * TZ; idx += 256) {
+    const int ky = idx / TZ, zz = idx - ky * TZ;
+    const cplx<T> v = ld<T>(S2, ((size_t)kx * 2 * N + ky) * N + z0 + zz);
+    ((ky & 1) ? bO : bE)[zz * PITCH + spec_pos<N>(ky >> 1)] = v;
+  }
+  __syncthreads();
+  fill_twl_any<T, N>(twl, tw, tid, 256);
+  __syncthreads();
+  {
+    const int g = tid / L, lane = tid - g * L;
+    for (int u = g; u < 2 * TZ; u += NG) {
+      cplx<T>* row = u < TZ ? bE + u * PITCH : bO + (u - TZ) * PITCH;
+      row_fft<T, N, +1>(row, lane, tw, twl);
+    }
+  }
+  __syncthreads();
+  void* S = d.vec[a.spec];
+  for (int idx = tid; idx < TZ * N; idx += 256) {
+    const int zz = idx / N, y = idx - zz * N;
+    stv<T>(S, ((size_t)kx * N + z0 + zz) * N + y, bE[zz * PITCH + y] + mulc(bO[zz * PITCH + y], tw[y]));
+  }
+}
+
+// Far field for large grids: the z-rows of a kx plane are streamed through LDS in chunks, so no
+// full plane is held.  Each thread owns one ky of the 2n-point accumulator.
+template <typename T, int N>
+__global__ __launch_bounds__(512) void k_ff_big(PassArgs a) {
+  constexpr int R = 16, PITCH = N + 1, NT = 512;
+  constexpr int L = row_lanes<N>();
+  constexpr int NG = NT / L;
+  __shared__ cplx<T> rE[R * PITCH];
+  __shared__ cplx<T> rO[R * PITCH];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> twl[twl_size<N>()];
+  int kx, slot;
+  plane_decode(a, kx, slot);
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  __syncthreads();
+  fill_twl_any<T, N>(twl, tw, tid, NT);
+  const void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (2 * N * N);
+  const int g = tid / L, lane = tid - g * L;
+  cplx<T> acc = {0, 0};
+  for (int z0 = 0; z0 < N; z0 += R) {
+    __syncthreads();
+    for (int idx = tid; idx < R * N; idx += NT) {
+      const int r = idx / N, y = idx - r * N;
+      const cplx<T> v = ld<T>(Sv, soff + (size_t)(z0 + r) * N + y);
+      rE[r * PITCH + y] = v;
+      rO[r * PITCH + y] = v * tw[y];
+    }
+    __syncthreads();
+    for (int u = g; u < 2 * R; u += NG) row_fft<T, N, -1>(u < R ? rE + u * PITCH : rO + (u - R) * PITCH, lane, tw, twl);
+    __syncthreads();
+    if (tid < 2 * N) {
+      const int ky = tid;
+      const cplx<T>* src = (ky & 1) ? rO : rE;
+      const int pos = spec_pos<N>(ky >> 1);
+      for (int r = 0; r < R; ++r) acc = acc + ld<T>(K, (size_t)(z0 + r) * 2 * N + ky) * src[r * PITCH + pos];
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * N) ((tid & 1) ? rO : rE)[spec_pos<N>(tid >> 1)] = acc;
+  __syncthreads();
+  if (g < 2) row_fft<T, N, +1>(g == 0 ? rE : rO, lane, tw, twl);
+  __syncthreads();
+  void* out = d.vec[a.sel];
+  for (int y = tid; y < N; y += NT) stv<T>(out, (size_t)kx * N + y, rE[y] + mulc(rO[y], tw[y]));
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(512) void k_ffT_big(PassArgs a) {
+  constexpr int R = 16, PITCH = N + 1, NT = 512;
+  constexpr int L = row_lanes<N>();
+  constexpr int NG = NT / L;
+  __shared__ cplx<T> rE[R * PITCH];
+  __shared__ cplx<T> rO[R * PITCH];
+  __shared__ cplx<T> hat[2 * N];
+  __shared__ cplx<T> tw[2 * N];
+  __shared__ cplx<T> twl[twl_size<N>()];
+  int kx, slot;
+  plane_decode(a, kx, slot);
+  if (!slot_active(a, slot)) return;
+  const int tid = threadIdx.x;
+  const SlotDesc& d = a.desc[slot];
+  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+  __syncthreads();
+  fill_twl_any<T, N>(twl, tw, tid, NT);
+  const void* rowv = d.vec[a.sel];
+  for (int y = tid; y < N; y += NT) {
+    const cplx<T> v = ld<T>(rowv, (size_t)kx * N + y);
+    hat[y] = v;
+    hat[N + y] = v * tw[y];
+  }
+  __syncthreads();
+  const int g = tid / L, lane = tid - g * L;
+  if (g < 2) row_fft<T, N, -1>(hat + g * N, lane, tw, twl);
+  __syncthreads();
+  void* Sv = d.vec[a.spec];
+  const size_t soff = (size_t)kx * N * N;
+  const int kxp = kx <= N ? kx : 2 * N - kx;
+  const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (2 * N * N);
+  for (int z0 = 0; z0 < N; z0 += R) {
+    for (int idx = tid; idx < R * 2 * N; idx += NT) {
+      const int r = idx / (2 * N), ky = idx - r * 2 * N;
+      const int pos = spec_pos<N>(ky >> 1);
+      const cplx<T> v = ld<T>(K, (size_t)(z0 + r) * 2 * N + ky) * hat[(ky & 1) * N + pos];
+      ((ky & 1) ? rO : rE)[r * PITCH + pos] = v;
+    }
+    __syncthreads();
+    for (int u = g; u < 2 * R; u += NG) row_fft<T, N, +1>(u < R ? rE + u * PITCH : rO + (u - R) * PITCH, lane, tw, twl);
+    __syncthreads();
+    for (int idx = tid; idx < R * N; idx += NT) {
+      const int r = idx / N, y = idx - r * N;
+      stv<T>(Sv, soff + (size_t)(z0 + r) * N + y, rE[r * PITCH + y] + mulc(rO[r * PITCH + y], tw[y]));
+    }
+    __syncthreads();
+  }
+}
+
+// =============================================================================================
 // BiCGSTAB vector update x += alpha p + omega s, r = s - omega t, with <rh, r> and ||r||^2.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_update(PassArgs a) {
@@ -1020,19 +1274,38 @@ static hipError_t update_t(const PassArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_update<T, N>), dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
+// A whole n x n plane fits in LDS up to n = 128 (complex64) and n = 96 (complex128).
+template <typename T, int N>
+constexpr bool split_plane() {
+  return sizeof(T) == 4 ? N > 128 : N > 96;
+}
 template <typename T, int N>
 static hipError_t yz_t(const PassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_yz3<T, N>), dim3(a.nslots * 2 * N * 2), dim3(Plane3Cfg<N>::NT), 0, s, a);
+  if constexpr (split_plane<T, N>()) {
+    using B = BigCfg<T, N>;
+    hipLaunchKernelGGL((k_yzA<T, N>), dim3(a.nslots * 2 * N * B::C), dim3(B::NT), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_yzB<T, N>), dim3(a.nslots * 2 * N * (N / 16)), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_yz3<T, N>), dim3(a.nslots * 2 * N * 2), dim3(Plane3Cfg<N>::NT), 0, s, a);
+  }
   return hipGetLastError();
 }
 template <typename T, int N>
 static hipError_t ff_t(const PassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_ff<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
+  if constexpr (split_plane<T, N>())
+    hipLaunchKernelGGL((k_ff_big<T, N>), dim3(a.nslots * 2 * N), dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_ff<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, int N>
 static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_ffT<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
+  if constexpr (split_plane<T, N>())
+    hipLaunchKernelGGL((k_ffT_big<T, N>), dim3(a.nslots * 2 * N), dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_ffT<T, N>), dim3(a.nslots * 2 * N), dim3(PlaneCfg<N>::NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1044,6 +1317,8 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
     case 64: return FN<float, 64>(__VA_ARGS__);           \
     case 96: return FN<float, 96>(__VA_ARGS__);           \
     case 128: return FN<float, 128>(__VA_ARGS__);         \
+    case 192: return FN<float, 192>(__VA_ARGS__);         \
+    case 256: return FN<float, 256>(__VA_ARGS__);         \
     default: return hipErrorInvalidValue;                 \
   }
 #define LS_DISPATCH_D(FN, n, ...)                         \
@@ -1053,6 +1328,9 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
     case 32: return FN<double, 32>(__VA_ARGS__);          \
     case 64: return FN<double, 64>(__VA_ARGS__);          \
     case 96: return FN<double, 96>(__VA_ARGS__);          \
+    case 128: return FN<double, 128>(__VA_ARGS__);        \
+    case 192: return FN<double, 192>(__VA_ARGS__);        \
+    case 256: return FN<double, 256>(__VA_ARGS__);        \
     default: return hipErrorInvalidValue;                 \
   }
 #define LS_DISPATCH(FN, dbl, n, ...)   \
@@ -1063,9 +1341,11 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
   }
 
 bool fused_supported(int n, bool dbl) {
-  if (dbl) return n == 8 || n == 16 || n == 32 || n == 64 || n == 96;
-  return n == 8 || n == 16 || n == 32 || n == 64 || n == 96 || n == 128;
+  (void)dbl;
+  return n == 8 || n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
 }
+
+bool plane_split(int n, bool dbl) { return dbl ? n > 96 : n > 128; }
 
 hipError_t launch_xfwd(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(xfwd_t, dbl, n, a, s) }
 hipError_t launch_xinv(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(xinv_t, dbl, n, a, s) }
