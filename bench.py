@@ -68,11 +68,25 @@ def main() -> int:
     wsFF = ctx.workspace(Q, _lib.LS_OP_FARFIELD)
     u = torch.empty((Q, n, n, n), dtype=cd, device=dev)
     stream = torch.cuda.current_stream()
+    grad_mode = W.kind == "gradient"
 
-    def step():
-        _, info = ctx.ls_forward(f, dirs, tol=W.tol, u=u, ws=wsF)
-        y = ctx.ls_farfield(f, u, ws=wsFF)
-        return info, y
+    if grad_mode:
+        # measured data: fields of the perturbed potential with 30 dB noise (untimed)
+        _, f_true = workloads.perturbed_potential(n, W.seed)
+        ft = torch.from_numpy(f_true).to(dev, rd)
+        ctx.ls_forward(ft, dirs, tol=W.tol, u=u, ws=wsF)
+        yhat = torch.from_numpy(workloads.add_noise(ctx.ls_farfield(ft, u, ws=wsFF).cpu().numpy())).to(dev, cd)
+        del ft
+        wsG = ctx.workspace(Q, _lib.LS_OP_GRAD)
+
+        def step():
+            loss, g, info = ctx.ls_grad(f, dirs, yhat, tol=W.tol, ws=wsG)
+            return info, g
+    else:
+        def step():
+            _, info = ctx.ls_forward(f, dirs, tol=W.tol, u=u, ws=wsF)
+            y = ctx.ls_farfield(f, u, ws=wsFF)
+            return info, y
 
     for i in range(args.warmup):
         step()
@@ -91,7 +105,7 @@ def main() -> int:
         print(f"[bench] step {k}: {times[-1]:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    value = Q * args.steps / total
+    value = (1 if grad_mode else Q) * args.steps / total
     last = infos[-1]
     iters = [i["iters"] for i in last]
     mvs = [i["matvecs"] for i in last]
@@ -159,11 +173,16 @@ def main() -> int:
     per_kernel = {k: {"avg_ms": round(v["avg_ms"], 4), "GB/s": round(v["gbs"], 1),
                       "hbm_frac": round(v["gbs"] / HBM_PEAK_GBS, 4)} for k, v in kern.items()}
 
+    if args.workload == "B":
+        metric = "LS solves/sec at 128^3x60 illum, FP32 vs plain at 1e-4 rel err; p50/p99 ms"
+    elif grad_mode:
+        metric = f"data-term gradients/sec at {n}^3x{Q} views ({W.precision}, tol {W.tol:g}); p50/p99 ms"
+    else:
+        metric = f"LS solves/sec at {n}^3x{Q} illum ({W.precision}, tol {W.tol:g}); p50/p99 ms"
     out = {
-        "metric": ("LS solves/sec at 128^3x60 illum, FP32 vs plain at 1e-4 rel err; p50/p99 ms" if args.workload == "B"
-                   else f"LS solves/sec at {n}^3x{Q} illum ({W.precision}, tol {W.tol:g}); p50/p99 ms"),
+        "metric": metric,
         "value": round(value, 3),
-        "unit": "solves/s",
+        "unit": "gradients/s" if grad_mode else "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -177,14 +196,17 @@ def main() -> int:
         "data": "synthetic (seeded 20-blob phantom, plane waves on a 45-degree cone)",
         "config": {"workload": W.name, "n": n, "padded_fft": 2 * n, "illuminations": Q, "tol": W.tol,
                    "detector": f"{n}x{n}", "p": W.p, "green_init_ms": round(t_init * 1e3, 1)},
-        "solve": {"iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
+        "solve": {"solves_per_step": len(last), "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
                   "matvecs_mean": float(np.mean(mvs)), "relres_true_max": float(max(relres))},
         "roofline": roof,
         "kernels": per_kernel,
     }
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["oracle_check"] = cpu_baseline(W, f_np, dirs, u, float(np.mean(mvs)))
+        if grad_mode:   # fields of f0 for the oracle's residual check (u held the data fields)
+            ctx.ls_forward(f, dirs, tol=W.tol, u=u, ws=wsF)
+        out["cpu_baseline"], out["oracle_check"] = cpu_baseline(W, f_np, dirs, u, float(np.mean(mvs)),
+                                                                per_step=len(last), grad_mode=grad_mode)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -210,7 +232,7 @@ def measured_traffic(workload, kernel):
         return None
 
 
-def cpu_baseline(W, f_np, dirs, u, mv_per_solve):
+def cpu_baseline(W, f_np, dirs, u, mv_per_solve, per_step=1, grad_mode=False):
     """The FP64 oracle timed on the host: one application of A = I - G diag f at the full size
     (two FFTs of (2n)^3) and one far field, scaled by the matvecs per solve of the GPU run.  The
     same matvec gives the oracle's residual of the GPU solution for illumination 0."""
@@ -233,6 +255,12 @@ def cpu_baseline(W, f_np, dirs, u, mv_per_solve):
     ofar.farfield_fft(f_np * u0, W.k, W.xg)
     t_ff = time.perf_counter() - t
     per_solve = t_mv * mv_per_solve + t_ff
+    if grad_mode:   # one gradient = per_step solves (forward and adjoint of every view)
+        base = {"value": round(1.0 / (per_solve * per_step), 8), "unit": "gradients/s", "cores": 1, "kind": "oracle",
+                "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
+                           f"{t_ff:.2f} s, scaled by {mv_per_solve:.1f} matvecs/solve x {per_step} solves/gradient; "
+                           f"kernel setup {t_setup:.1f} s excluded")}
+        return base, {"oracle_relres_q0": relres, "tol": W.tol}
     base = {"value": round(1.0 / per_solve, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
                        f"{t_ff:.2f} s, scaled by {mv_per_solve:.1f} matvecs/solve; kernel setup {t_setup:.1f} s "

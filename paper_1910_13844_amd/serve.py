@@ -12,7 +12,7 @@ reductions in a fixed order).
 Engines: ``GpuEngine`` drives libls through ``api``; tests substitute a CPU engine with the same
 methods to exercise the scheduler without a GPU.
 
-    python -m paper_1910_13844_amd.serve --requests 40 --rate 20 --grids 64,96,128
+    python -m paper_1910_13844_amd.serve [--requests 400] [--rate 20] [--grids 64,96,128,192] [--baseline]
 """
 from __future__ import annotations
 
@@ -81,8 +81,10 @@ class Scheduler:
       finish_grad(req)                      -> after all adjoint solves: gradient accumulation
     """
 
-    def __init__(self, engine, iters_per_step: int = 2, clock: Callable[[], float] = time.perf_counter):
+    def __init__(self, engine, iters_per_step: int = 2, clock: Callable[[], float] = time.perf_counter,
+                 progress: int = 0):
         self.e = engine
+        self.progress = progress
         self.iters = iters_per_step
         self.clock = clock
         self.pending: Dict[int, Deque[Job]] = {}
@@ -99,7 +101,6 @@ class Scheduler:
 
     def submit(self, req: Request):
         self._pool(req.n)
-        self.e.prepare(req)
         self.left[(req.rid, "fwd")] = req.Q
         for q in range(req.Q):
             self.pending[req.n].append(Job(req, q, "fwd"))
@@ -109,6 +110,9 @@ class Scheduler:
         for i, s in enumerate(slots):
             if s is None and self.pending[n]:
                 job = self.pending[n].popleft()
+                if job.phase == "fwd" and job.q == 0:
+                    # per-request device buffers exist only from the first admission to completion
+                    self.e.prepare(job.req)
                 job.slot = i
                 self.e.admit(n, i, job)
                 slots[i] = job
@@ -130,16 +134,21 @@ class Scheduler:
                 if job.phase == "fwd":
                     self.e.finish_forward(req)
                     if req.kind == "grad":
+                        # adjoint solves go ahead of queued work: the request already holds its
+                        # fields, and finishing it first bounds both memory and its latency
                         self.left[(req.rid, "adj")] = req.Q
-                        for q in range(req.Q):
-                            self.pending[n].append(Job(req, q, "adj"))
+                        self.pending[n].extendleft(Job(req, q, "adj") for q in reversed(range(req.Q)))
                     else:
-                        req.done_time = self.clock() - t0
-                        self.completed.append(req)
+                        self._complete(req, t0)
                 else:
                     self.e.finish_grad(req)
-                    req.done_time = self.clock() - t0
-                    self.completed.append(req)
+                    self._complete(req, t0)
+
+    def _complete(self, req: Request, t0: float):
+        req.done_time = self.clock() - t0
+        self.completed.append(req)
+        if self.progress and len(self.completed) % self.progress == 0:
+            print(f"[serve] {len(self.completed)} requests done at {req.done_time:.1f} s", file=sys.stderr, flush=True)
 
     def busy(self) -> bool:
         return any(s is not None for pool in self.slots.values() for s in pool) or any(self.pending.values())
@@ -179,7 +188,7 @@ class GpuEngine:
     """Scheduler engine backed by libls on one GPU."""
 
     def __init__(self, hbm_budget_gb: float = 120.0, tol: float = 1e-5, maxit: int = 500, prec: str = "c64",
-                 device: str = "cuda:0", max_slots: int = 64):
+                 device: str = "cuda:0", max_slots: int = 64, inputs: Optional[dict] = None):
         import torch
 
         from . import _lib, api, workloads
@@ -191,6 +200,9 @@ class GpuEngine:
         self.ctx: Dict[int, "api.Context"] = {}
         self.pool: Dict[int, "api.Batch"] = {}
         self.data: Dict[int, dict] = {}
+        # request inputs (potential, directions, measurements) keyed by request id; may be shared
+        # between engines on the same device so that a trace is generated once
+        self.inputs: Dict[int, dict] = {} if inputs is None else inputs
 
     def _ctx(self, n):
         if n not in self.ctx:
@@ -205,31 +217,42 @@ class GpuEngine:
         self.pool[n] = self.api.Batch(c, cap, tol=self.tol, maxit=self.maxit)
         return cap
 
-    def preload(self, trace: Sequence[Request]):
+    def preload(self, trace: Sequence[Request], workers: int = 8):
         """Generate every request's inputs before the trace starts (not part of the served work):
         the potential, the illumination directions and, for gradient requests, synthetic measurements
-        of a perturbed phantom."""
+        of a perturbed phantom.  Phantoms are generated on `workers` host threads."""
+        import concurrent.futures as cf
+
         torch = self.torch
-        for req in trace:
-            c = self._ctx(req.n)
+        todo = [r for r in trace if r.rid not in self.inputs]
+
+        def phantoms(req):
             f = self.wl.blob_potential(req.seed, req.n, dn_max=0.05)
-            d = {"f": torch.from_numpy(f).to(self.device, c.rdtype), "dirs": self.wl.cone_dirs(req.Q, req.theta)}
+            pert = None
             if req.kind == "grad":
                 pert = self.wl.blob_potential(req.seed + 100000, req.n, nblobs=5, sigma_range=(2.0, 5.0),
                                               dn_max=0.01)
-                ft = torch.from_numpy(f + pert).to(self.device, c.rdtype)
-                ut, _ = c.ls_forward(ft, d["dirs"], tol=self.tol)
-                d["y_meas"] = c.ls_farfield(ft, ut)
-                del ut
-            self.data[req.rid] = d
+            return f, pert
+
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            for req, (f, pert) in zip(todo, ex.map(phantoms, todo)):
+                c = self._ctx(req.n)
+                d = {"f": torch.from_numpy(f).to(self.device, c.rdtype), "dirs": self.wl.cone_dirs(req.Q, req.theta)}
+                if pert is not None:
+                    ft = torch.from_numpy(f + pert).to(self.device, c.rdtype)
+                    ut, _ = c.ls_forward(ft, d["dirs"], tol=self.tol)
+                    d["y_meas"] = c.ls_farfield(ft, ut)
+                    del ut, ft
+                self.inputs[req.rid] = d
         torch.cuda.synchronize()
 
     def prepare(self, req: Request):
         c = self._ctx(req.n)
-        d = self.data[req.rid]
+        d = dict(self.inputs[req.rid])
         d["u"] = self.torch.empty((req.Q, req.n, req.n, req.n), dtype=c.cdtype, device=self.device)
         if req.kind == "grad":
             d["w"] = self.torch.empty_like(d["u"])
+        self.data[req.rid] = d
 
     def admit(self, n, slot, job: Job):
         d = self.data[job.req.rid]
@@ -258,6 +281,7 @@ class GpuEngine:
             d["b"] = c.ls_farfield_adj(r, conj=True)
         else:
             req.outputs["y"] = d["y"]
+            self.data.pop(req.rid, None)
 
     def finish_grad(self, req: Request):
         d = self.data[req.rid]
@@ -302,29 +326,59 @@ def one_at_a_time(engine_factory, trace: Sequence[Request]) -> dict:
             e.finish_forward(req)
         req.done_time = time.perf_counter() - t0
         done.append(req)
+        if len(done) % 50 == 0:
+            print(f"[serve] one-at-a-time: {len(done)} requests done at {req.done_time:.1f} s", file=sys.stderr,
+                  flush=True)
     torch.cuda.synchronize()
     return summarize(done, time.perf_counter() - t0, solves)
 
 
+def _max_rel_diff(a: Sequence[Request], b: Sequence[Request]) -> float:
+    """Largest relative difference between the outputs (detector fields or gradients) that two runs
+    produced for the same requests."""
+    ob = {r.rid: r.outputs for r in b}
+    worst = 0.0
+    for r in a:
+        for key in ("y", "grad"):
+            x, y = r.outputs.get(key), ob.get(r.rid, {}).get(key)
+            if x is not None and y is not None:
+                d = float((x - y).abs().pow(2).sum().sqrt() / y.abs().pow(2).sum().sqrt().clamp_min(1e-300))
+                worst = max(worst, d)
+    return worst
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=40)
+    ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--rate", type=float, default=20.0)
-    ap.add_argument("--grids", default="64,96,128")
+    ap.add_argument("--grids", default="64,96,128,192")
     ap.add_argument("--qmax", type=int, default=60)
     ap.add_argument("--budget-gb", type=float, default=120.0)
     ap.add_argument("--baseline", action="store_true", help="also run the one-solve-at-a-time baseline")
     args = ap.parse_args(argv)
+    import torch
+
     grids = [int(g) for g in args.grids.split(",")]
     mk = lambda: poisson_trace(args.requests, args.rate, grids, args.qmax)  # noqa: E731
-    eng = GpuEngine(hbm_budget_gb=args.budget_gb)
+    inputs: dict = {}
+    eng = GpuEngine(hbm_budget_gb=args.budget_gb, inputs=inputs)
     trace = mk()
+    t = time.perf_counter()
     eng.preload(trace)
-    sched = Scheduler(eng)
+    print(f"[serve] inputs for {len(trace)} requests ready in {time.perf_counter() - t:.1f} s", file=sys.stderr,
+          flush=True)
+    sched = Scheduler(eng, progress=50)
     res = {"continuous": sched.run(trace)}
+    print(f"[serve] continuous: {res['continuous']}", file=sys.stderr, flush=True)
     if args.baseline:
-        res["one_at_a_time"] = one_at_a_time(lambda: GpuEngine(hbm_budget_gb=args.budget_gb), mk())
-    res["config"] = {"requests": args.requests, "rate": args.rate, "grids": grids, "qmax": args.qmax}
+        del sched, eng
+        torch.cuda.empty_cache()
+        trace_b = mk()
+        res["one_at_a_time"] = one_at_a_time(lambda: GpuEngine(hbm_budget_gb=args.budget_gb, inputs=inputs), trace_b)
+        res["alone_vs_mix_max_rel"] = _max_rel_diff(trace, trace_b)
+    nsolve = sum(r.Q * (2 if r.kind == "grad" else 1) for r in trace)
+    res["config"] = {"requests": args.requests, "rate": args.rate, "grids": grids, "qmax": args.qmax,
+                     "solves_in_trace": nsolve, "trace_seconds": max(r.arrival for r in trace)}
     print(json.dumps(res), flush=True)
     return 0
 

@@ -100,6 +100,7 @@ class Workload:
     phantom: str            # "sphere" or "blobs"
     seed: int = 0
     dn_max: float = 0.05
+    kind: str = "forward"   # "forward": solves + far fields; "gradient": data-term gradient at f0
 
     @property
     def k(self) -> float:
@@ -129,7 +130,9 @@ WORKLOADS: Dict[str, Workload] = {
     # 256^3 blob phantom with stronger contrast, 60 illuminations, complex64, tol 1e-5.
     "C": Workload("blobs256_q60_c64", 256, 4, 60, 45.0, 1e-5, "c64", "blobs", seed=1, dn_max=0.1),
     # 128^3 gradient workload, 40 illuminations on a 40 degree cone.
-    "D": Workload("grad128_q40_c64", 128, 4, 40, 40.0, 1e-5, "c64", "blobs", seed=2, dn_max=0.05),
+    # f0 = phantom seed 2; data from f0 + a 5-blob perturbation (seed 3) with 30 dB noise (seed 4).
+    "D": Workload("grad128_q40_c64", 128, 4, 40, 40.0, 1e-5, "c64", "blobs", seed=2, dn_max=0.05,
+                  kind="gradient"),
 }
 
 
