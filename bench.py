@@ -117,31 +117,26 @@ def main() -> int:
     N = n ** 3
     Nc = N * c
     ker_bytes = (n + 1) * 4 * n * n * c
-    # grids whose n x n plane exceeds LDS run the (y,z) pass as two kernels around a
-    # [kx][ky][z] spectrum (n > 128 in complex64, n > 96 in complex128)
-    split = n > (96 if W.precision == "c128" else 128)
     passes = {
         "k_xfwd": (0, Q * 6.5 * Nc, 2),
-        "k_yz": (1, Q * (12 if split else 6) * Nc + ker_bytes, 2),
-        "k_xinv": (2, Q * (5 if split else 7) * Nc, 2),
+        "k_yz": (1, Q * 6 * Nc + ker_bytes, 2),
+        "k_xinv": (2, Q * 7 * Nc, 2),
         "k_update": (3, Q * 7 * Nc, 1),
     }
     # algorithmic bytes per launch (units of N*c per slot):
     #   k_xfwd (p-update prologue): read r p v (3) + f (0.5), write p (1) + x-spectrum (2)
-    #   k_yz   read x-spectrum plane (2), write the two ky-parity halves (4), + kernel once;
-    #          split: class kernel reads 2, writes the [kx][ky][z] spectrum (4), z-tile kernel
-    #          reads it (4) and writes the x-spectrum back (2)
-    #   k_xinv (v epilogue): read both halves (4) [split: one spectrum, 2] + p, rh (2), write v (1)
+    #   k_yz   read the x-spectrum (2), write the class-split (y,z) output (4), + kernel once
+    #   k_xinv (v epilogue): read the class output (4) + p, rh (2), write v (1)
     #   k_update: read x p s t rh (5), write x r (2)
-    # FFT flops of the (y,z) pass (5 L log2 L per L-point transform of the split 2n-point DFTs)
+    # FFT flops of the (y,z) pass with C ky classes of M = 2n/C points (5 L log2 L per L-point
+    # transform): per (slot, kx) C x [n forward + n inverse M-point row DFTs + M columns x 4
+    # n-point DFTs (z-convolution)] + pointwise kernel products
     import math
-    fft_flops = 5 * n * math.log2(n)
-    if split:
-        Mc = {192: 96, 256: 64}[n] if W.precision == "c64" else {128: 64, 192: 32, 256: 32}[n]
-        yz_flops = Q * 2 * n * (2 * n * 5 * n * math.log2(Mc) + 2 * n * 4 * fft_flops + 2 * n * fft_flops
-                                + 2 * n * n * 6)
-    else:
-        yz_flops = Q * 2 * n * ((2 * n + 2 * n) * fft_flops + 8 * n * fft_flops + 2 * 2 * n * n * 6)
+    C = {True: {8: 2, 16: 2, 32: 2, 64: 2, 96: 6, 128: 8, 192: 12, 256: 16},
+         False: {8: 2, 16: 2, 32: 2, 64: 2, 96: 2, 128: 4, 192: 12, 256: 16}}[W.precision == "c128"][n]
+    Mc = 2 * n // C
+    yz_flops = Q * 2 * n * C * (2 * n * 5 * Mc * math.log2(Mc) + Mc * 4 * 5 * n * math.log2(n)
+                                + 2 * Mc * n * 6)
     prof_ws = torch.empty_like(wsF)
     prof_u = u.clone()
     kern = {}

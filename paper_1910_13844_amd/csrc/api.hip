@@ -127,15 +127,12 @@ struct Run {
   }
 };
 
-// Where k_xinv finds the output of the (y,z) pass.
+// k_xinv reads the class-major output of the (y,z) pass, which starts at V_SPE and runs over
+// V_SPE and V_SPO (4 N complex per slot); spec2 >= 0 selects that mode.
 void xinv_source(const ls_ctx* c, PassArgs& a) {
-  if (plane_split(c->n, c->dbl)) {
-    a.spec = V_SPEC;
-    a.spec2 = -1;
-  } else {
-    a.spec = V_SPE;
-    a.spec2 = V_SPO;
-  }
+  (void)c;
+  a.spec = V_SPE;
+  a.spec2 = V_SPO;
 }
 
 int matvec(const Run& r, int pro, int sel, int epi, int esel, int esel2, uint32_t mask) {

@@ -18,8 +18,8 @@ enum Vec : int {
   V_SPEC = 7,  // x-spectrum scratch: [2n kx][nz][n y]
   V_B = 8,     // stored right-hand side (null: plane wave)
   V_AUX = 9,   // detector-plane buffer or other per-slot I/O
-  V_SPE = 10,  // (y,z)-convolved x-spectrum, even-ky half
-  V_SPO = 11,  // (y,z)-convolved x-spectrum, odd-ky half
+  V_SPE = 10,  // (y,z)-convolved x-spectrum by ky class, [c][2n kx][n z][2n/C]; spans V_SPE and V_SPO
+  V_SPO = 11,  // second half of that region (class 1 of the parity split)
   V_COUNT = 12
 };
 

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
 
 // =============================================================================================
 // k_xinv: inverse x-DFTs (even + modulated odd half), crop to n, epilogue and FP64 partials.
-template <typename T, int N, int EPI>
+template <typename T, int N, int EPI, int CL>
 __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   using X = XCfg<N>;
   constexpr int TY = X::TY, NYT = X::NYT, PITCH = X::PITCH, IT = X::IT, IT2 = X::IT2;
@@ -303,38 +303,80 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   __shared__ cplx<T> twl[twl_size<N>()];
   __shared__ double red[6 * 4];
   const int tid = threadIdx.x;
+  // CL = 1: plain x-spectrum [kx][z][y].  CL > 1: class-major output of the (y,z) pass,
+  // [c][kx][z][j] with rows of CM = 2n / CL (periodic in y with period CM); the value at y is
+  // sum_c exp(+i pi c y / n) Y_c[y mod CM].
+  constexpr int CM = CL == 1 ? N : 2 * N / CL;
+  constexpr int TPP = CM / TY;   // y tiles per period
+  constexpr int FA = NYT / TPP;  // periods per row: tiles reading the same class rows
   const int per = a.nz * NYT;
-  const int slot = blockIdx.x / per;
-  const int blk = blockIdx.x - slot * per;
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  // consecutive blocks on one XCD are the FA tiles of one (slot, z) that read the same class
+  // values, so all but the first find them in L2
+  const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int slot = lin / per;
+  const int blk = lin - slot * per;
   if (!slot_active(a, slot)) return;
   const int z = blk / NYT;
-  const int y0 = (blk - z * NYT) * TY;
+  const int tr = blk - z * NYT;
+  const int y0 = ((tr / FA) + (tr % FA) * TPP) * TY;
   const SlotDesc& d = a.desc[slot];
   for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
   {
+    constexpr int CB = (CL > 1 && sizeof(T) == 4 && IT2 <= 16) ? 2 : 1;  // classes per batch of loads
+    static_assert(CL == 1 || (CM % TY == 0 && CL % CB == 0), "y tiles must stay inside one period");
     const void* spec = d.vec[a.spec];
-    const void* spo = a.spec2 >= 0 ? d.vec[a.spec2] : nullptr;
-    cplx<T> e[IT2], o[IT2];
+    const int j0 = y0 % CM;
+    // sum_c w^c Y_c with w = exp(+i pi y / n), by Horner's rule from the last class down; the
+    // loads of CB classes are issued together
+    auto load = [&](cplx<T>(&v)[CB][IT2], int c0) {
 #pragma unroll
-    for (int it = 0; it < IT2; ++it) {
-      const int i = tid + it * 256;
-      if (i < 2 * N * TY) {
-        const size_t gi = ((size_t)(i / TY) * a.nz + z) * N + y0 + i % TY;
-        e[it] = ld<T>(spec, gi);
-        if (spo) o[it] = ld<T>(spo, gi);
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int it = 0; it < IT2; ++it) {
+          const int i = tid + it * 256;
+          if (i < 2 * N * TY) {
+            const size_t gi = (((size_t)(c0 + cb) * 2 * N + i / TY) * a.nz + z) * CM + j0 + i % TY;
+            v[cb][it] = ld<T>(spec, gi);
+          }
+        }
+    };
+    cplx<T> acc[IT2];
+    {
+      cplx<T> v[CB][IT2];
+      load(v, CL - CB);
+      __syncthreads();  // tw visible
+      fill_twl_any<T, N>(twl, tw, tid, 256);
+#pragma unroll
+      for (int it = 0; it < IT2; ++it) acc[it] = v[CB - 1][it];
+      if constexpr (CB > 1) {
+        const cplx<T> w = conj(tw[y0 + tid % TY]);
+#pragma unroll
+        for (int cb = CB - 2; cb >= 0; --cb)
+#pragma unroll
+          for (int it = 0; it < IT2; ++it) acc[it] = acc[it] * w + v[cb][it];
       }
     }
-    __syncthreads();
-    fill_twl_any<T, N>(twl, tw, tid, 256);
+    if constexpr (CL > CB) {
+      const cplx<T> w = conj(tw[y0 + tid % TY]);
+#pragma unroll(CL / CB <= 2 ? 2 : 1)
+      for (int c0 = CL - 2 * CB; c0 >= 0; c0 -= CB) {
+        cplx<T> v[CB][IT2];
+        load(v, c0);
+#pragma unroll
+        for (int cb = CB - 1; cb >= 0; --cb)
+#pragma unroll
+          for (int it = 0; it < IT2; ++it) acc[it] = acc[it] * w + v[cb][it];
+      }
+    }
 #pragma unroll
     for (int it = 0; it < IT2; ++it) {
       const int i = tid + it * 256;
       if (i < 2 * N * TY) {
         const int yy = i % TY;
         const int kx = i / TY;
-        // y-parity halves of the (y,z) convolution: value = E + exp(+i pi y / n) O
-        const cplx<T> v = spo ? e[it] + mulc(o[it], tw[y0 + yy]) : e[it];
-        ((kx & 1) ? bufO : bufE)[yy * PITCH + spec_pos<N>(kx >> 1)] = v;
+        ((kx & 1) ? bufO : bufE)[yy * PITCH + spec_pos<N>(kx >> 1)] = acc[it];
       }
     }
   }
@@ -726,54 +768,51 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
 }
 
 // =============================================================================================
-// Grid sizes whose n x n plane does not fit in LDS (complex64 n = 192, 256; complex128 n = 128).
-// The (y,z) pass is split in two kernels around a [kx][ky][z] spectrum:
-//   k_yzA  one workgroup per (slot, kx, ky class c): the zero-padded 2n-point y-DFT restricted to
-//          ky = c (mod C) is an M-point DFT (M = 2n / C) of the row folded with exp(-i pi c y / n);
-//          each of the M ky columns is z-convolved with the kernel; written as [kx][ky][z].
-//   k_yzB  one workgroup per (slot, kx, tile of 16 z): cropped inverse 2n-point y-DFT (even and odd
-//          ky halves, as in k_xinv) and written back as [kx][z][y], which k_xinv reads as usual.
-// M: ky columns per class, the largest supported transform length for which the N x M slab
-// (pitch M + 1) fits in LDS.
+// Class-split (y,z) pass.  The ky frequencies of the zero-padded 2n-point y-DFT are split into C
+// classes ky = c (mod C).  For one class the DFT reduces to an M-point DFT (M = 2n / C) of the row
+// folded onto M points with the twiddle exp(-i pi c y / n):
+//     z_c[j] = sum_{m < n/M} x[j + m M] exp(-i pi c (j + m M) / n),
+// and the cropped inverse of that class is the M-point inverse DFT Y_c, periodic in y with
+// period M, times exp(+i pi c y / n).  One workgroup per (slot, kx, c) holds an n x M slab in LDS:
+// fold, forward row DFTs, z-convolution of its M columns, inverse row DFTs, and writes Y_c to the
+// class-major spectrum [c][kx][z][j]; k_xinv sums the classes.  C = 2 is the parity split of
+// k_yz3 (no fold).  Larger C keeps the slab small enough for several workgroups per CU, so the
+// global-memory phases of one workgroup overlap the transforms of another, and it lets grids
+// whose whole n x n plane exceeds LDS (n = 192, 256) run the same way.
 template <typename T, int N>
-constexpr int big_m() {
-  if constexpr (sizeof(T) == 4)
-    return N == 192 ? 96 : 64;
-  else
-    return N == 128 ? 64 : 32;
-}
-
-template <typename T, int N>
-struct BigCfg {
-  static constexpr int M = big_m<T, N>();
-  static constexpr int C = 2 * N / M;
-  static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
+struct ClassCfg {
+  // number of classes; 2 = k_yz3
+  static constexpr int C = sizeof(T) == 4 ? (N <= 96 ? 2 : (N == 128 ? 4 : (N == 192 ? 12 : 16)))
+                                          : (N <= 64 ? 2 : (N == 96 ? 6 : (N == 128 ? 8 : (N == 192 ? 12 : 16))));
+  static constexpr int M = 2 * N / C;
+  static constexpr int NT = 256;
   static constexpr int PITCH = M + 1;
-  static_assert(N % M == 0, "fold needs n / M integral");
+  static_assert(C == 2 || (HasSplit<M>::value && N % M == 0 && M % 16 == 0), "class slab shape");
 };
 
+// twl[k1 * L + l] = exp(-2 pi i l k1 / M) from the 2n-entry table (stride 2n / M)
 template <typename T, int M, int TWS>
 __device__ __forceinline__ void fill_twl_stride(cplx<T>* twl, const cplx<T>* tw, int tid, int nt) {
-  // twl[k1 * L + l] = exp(-2 pi i l k1 / M) from a table of exp(-2 pi i m / (M TWS))
-  if constexpr (HasSplit<M>::value) {
-    constexpr int L = Split<M>::L, E = Split<M>::E;
-    for (int i = tid; i < L * E; i += nt) {
-      const int k1 = i / L, l = i - k1 * L;
-      twl[i] = tw[TWS * l * k1];
-    }
+  constexpr int L = Split<M>::L, E = Split<M>::E;
+  for (int i = tid; i < L * E; i += nt) {
+    const int k1 = i / L, l = i - k1 * L;
+    twl[i] = tw[TWS * l * k1];
   }
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__((BigCfg<T, N>::NT)) void k_yzA(PassArgs a) {
-  using B = BigCfg<T, N>;
-  constexpr int C = B::C, M = B::M, NT = B::NT, PITCH = B::PITCH, F = N / M;
-  __shared__ cplx<T> plane[N * PITCH];
+__global__ __launch_bounds__(256) void k_yzc(PassArgs a) {
+  using CC = ClassCfg<T, N>;
+  constexpr int C = CC::C, M = CC::M, F = N / M, NT = CC::NT, PITCH = CC::PITCH;
+  constexpr int LM = Split<M>::L;
+  __shared__ cplx<T> slab[N * PITCH];
   __shared__ cplx<T> tw[2 * N];
-  __shared__ cplx<T> twlM[twl_size<M>()];
+  __shared__ cplx<T> twlM[M];
   __shared__ cplx<T> twlN[twl_size<N>()];
   const int nb = gridDim.x;
   const int b = blockIdx.x;
+  // consecutive blocks on one XCD: the C classes of one (kx, slot) plane (the plane is read once
+  // from HBM, then from L2), and all slots of one kx (the kernel plane stays in L2)
   const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
   const int c = lin % C;
   const int ks = lin / C;
@@ -782,98 +821,79 @@ __global__ __launch_bounds__((BigCfg<T, N>::NT)) void k_yzA(PassArgs a) {
   if (!slot_active(a, slot)) return;
   const int tid = threadIdx.x;
   const SlotDesc& d = a.desc[slot];
-  for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
   const void* Sv = d.vec[a.spec];
   const size_t soff = (size_t)kx * N * N;
   const int kxp = kx <= N ? kx : 2 * N - kx;
   const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
-  __syncthreads();
+  // fold, with the loads of a chunk issued together
+  {
+    constexpr int PER = N * M / NT;
+    constexpr int CH0 = 32 / F < 8 ? 32 / F : 8;  // at most 32 loads in flight per thread
+    constexpr int CH = PER % CH0 == 0 ? CH0 : (PER % 4 == 0 ? 4 : (PER % 2 == 0 ? 2 : 1));
+    static_assert(PER % CH == 0 && PER * NT == N * M, "fold chunks");
+    for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+#pragma unroll 1
+    for (int k0 = 0; k0 < PER; k0 += CH) {
+      cplx<T> xv[CH][F];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int idx = tid + (k0 + k) * NT;
+        const int zz = idx / M, j = idx - zz * M;
+#pragma unroll
+        for (int m = 0; m < F; ++m) xv[k][m] = ld<T>(Sv, soff + (size_t)zz * N + j + m * M);
+      }
+      if (k0 == 0) __syncthreads();  // tw visible
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int idx = tid + (k0 + k) * NT;
+        const int zz = idx / M, j = idx - zz * M;
+        cplx<T> acc = c == 0 ? xv[k][0] : xv[k][0] * tw[(c * j) % (2 * N)];
+#pragma unroll
+        for (int m = 1; m < F; ++m) acc = acc + xv[k][m] * tw[(c * (j + m * M)) % (2 * N)];
+        slab[zz * PITCH + j] = acc;
+      }
+    }
+  }
   fill_twl_stride<T, M, C>(twlM, tw, tid, NT);
   fill_twl_any<T, N>(twlN, tw, tid, NT);
-  // fold the zero-padded row onto M points: z_c[j] = sum_m x[j + m M] exp(-i pi c (j + m M) / n)
-  for (int idx = tid; idx < N * M; idx += NT) {
-    const int zz = idx / M, j = idx - zz * M;
-    cplx<T> acc = {0, 0};
-#pragma unroll
-    for (int m = 0; m < F; ++m) {
-      const int y = j + m * M;
-      acc = acc + ld<T>(Sv, soff + (size_t)zz * N + y) * tw[(c * y) % (2 * N)];
-    }
-    plane[zz * PITCH + j] = acc;
-  }
   __syncthreads();
   {
-    constexpr int LM = row_lanes<M>();
     constexpr int G = NT / LM;
     const int g = tid / LM, lane = tid - g * LM;
-    for (int r = g; r < N; r += G) row_fft<T, M, -1, C>(plane + r * PITCH, lane, tw, twlM);
+    for (int idx = g; idx < N; idx += G) row_fft<T, M, -1>(slab + spreadL<N, LM>(idx) * PITCH, lane, tw, twlM);
   }
   __syncthreads();
   if constexpr (HasSplit<N>::value) {
     constexpr int L = Split<N>::L;
     constexpr int G = NT / L;
     const int g = tid / L, lane = tid - g * L;
-    for (int j = g; j < M; j += G) {
+    for (int idx = g; idx < M; idx += G) {
+      const int j = spreadL<M, L>(idx);
       const int ky = c + C * spec_freq<M>(j);
-      zconv4<T, N, PITCH>(plane + j, lane, tw, twlN, K + (size_t)ky * (2 * N));
+      zconv4<T, N, PITCH>(slab + j, lane, tw, twlN, K + (size_t)ky * (2 * N));
     }
   } else {
     constexpr int L = Lanes<N>::value;
     constexpr int G = NT / L;
     const int g = tid / L, lane = tid - g * L;
-    for (int j = g; j < M; j += G) {
+    for (int idx = g; idx < M; idx += G) {
+      const int j = spreadL<M, L>(idx);
       const int ky = c + C * spec_freq<M>(j);
-      zconv<T, N>(plane + j, PITCH, lane, tw, K + (size_t)ky * (2 * N));
+      zconv<T, N>(slab + j, PITCH, lane, tw, K + (size_t)ky * (2 * N));
     }
   }
-  __syncthreads();
-  void* S2 = d.vec[V_SPE];
-  for (int idx = tid; idx < N * M; idx += NT) {
-    const int j = idx / N, zz = idx - j * N;
-    const int ky = c + C * spec_freq<M>(j);
-    stv<T>(S2, ((size_t)kx * 2 * N + ky) * N + zz, plane[zz * PITCH + j]);
-  }
-}
-
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_yzB(PassArgs a) {
-  constexpr int TZ = 16, PITCH = N + 1;
-  constexpr int L = row_lanes<N>();
-  constexpr int NG = 256 / L;
-  __shared__ cplx<T> bE[TZ * PITCH];
-  __shared__ cplx<T> bO[TZ * PITCH];
-  __shared__ cplx<T> tw[2 * N];
-  __shared__ cplx<T> twl[twl_size<N>()];
-  const int per = 2 * N * (N / TZ);
-  const int slot = blockIdx.x / per;
-  const int rem = blockIdx.x - slot * per;
-  const int kx = rem / (N / TZ);
-  const int z0 = (rem - kx * (N / TZ)) * TZ;
-  if (!slot_active(a, slot)) return;
-  const int tid = threadIdx.x;
-  const SlotDesc& d = a.desc[slot];
-  for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
-  const void* S2 = d.vec[V_SPE];
-  for (int idx = tid; idx < 2 * N * TZ; idx += 256) {
-    const int ky = idx / TZ, zz = idx - ky * TZ;
-    const cplx<T> v = ld<T>(S2, ((size_t)kx * 2 * N + ky) * N + z0 + zz);
-    ((ky & 1) ? bO : bE)[zz * PITCH + spec_pos<N>(ky >> 1)] = v;
-  }
-  __syncthreads();
-  fill_twl_any<T, N>(twl, tw, tid, 256);
   __syncthreads();
   {
-    const int g = tid / L, lane = tid - g * L;
-    for (int u = g; u < 2 * TZ; u += NG) {
-      cplx<T>* row = u < TZ ? bE + u * PITCH : bO + (u - TZ) * PITCH;
-      row_fft<T, N, +1>(row, lane, tw, twl);
-    }
+    constexpr int G = NT / LM;
+    const int g = tid / LM, lane = tid - g * LM;
+    for (int idx = g; idx < N; idx += G) row_fft<T, M, +1>(slab + spreadL<N, LM>(idx) * PITCH, lane, tw, twlM);
   }
   __syncthreads();
-  void* S = d.vec[a.spec];
-  for (int idx = tid; idx < TZ * N; idx += 256) {
-    const int zz = idx / N, y = idx - zz * N;
-    stv<T>(S, ((size_t)kx * N + z0 + zz) * N + y, bE[zz * PITCH + y] + mulc(bO[zz * PITCH + y], tw[y]));
+  void* Ov = d.vec[V_SPE];
+  const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
+  for (int i = tid; i < N * M; i += NT) {
+    const int zz = i / M, j = i - zz * M;
+    stv<T>(Ov, ooff + i, slab[zz * PITCH + j]);
   }
 }
 
@@ -1257,13 +1277,19 @@ static hipError_t xfwd_t(const PassArgs& a, hipStream_t s) {
 template <typename T, int N>
 static hipError_t xinv_t(const PassArgs& a, hipStream_t s) {
   const dim3 nb(a.nslots * a.nz * XCfg<N>::NYT);
+  constexpr int CL = ClassCfg<T, N>::C;
+  if (a.spec2 < 0) {  // plain spectrum (far-field transpose)
+    if (a.mode != EPI_STORE) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, 1>), nb, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   switch (a.mode) {
-    case EPI_STORE: hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE>), nb, dim3(256), 0, s, a); break;
-    case EPI_AXV: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXV>), nb, dim3(256), 0, s, a); break;
-    case EPI_AXT: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXT>), nb, dim3(256), 0, s, a); break;
-    case EPI_R0: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0>), nb, dim3(256), 0, s, a); break;
-    case EPI_TRUE: hipLaunchKernelGGL((k_xinv<T, N, EPI_TRUE>), nb, dim3(256), 0, s, a); break;
-    case EPI_AX: hipLaunchKernelGGL((k_xinv<T, N, EPI_AX>), nb, dim3(256), 0, s, a); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, CL>), nb, dim3(256), 0, s, a); break;
+    case EPI_AXV: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXV, CL>), nb, dim3(256), 0, s, a); break;
+    case EPI_AXT: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXT, CL>), nb, dim3(256), 0, s, a); break;
+    case EPI_R0: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0, CL>), nb, dim3(256), 0, s, a); break;
+    case EPI_TRUE: hipLaunchKernelGGL((k_xinv<T, N, EPI_TRUE, CL>), nb, dim3(256), 0, s, a); break;
+    case EPI_AX: hipLaunchKernelGGL((k_xinv<T, N, EPI_AX, CL>), nb, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1281,15 +1307,11 @@ constexpr bool split_plane() {
 }
 template <typename T, int N>
 static hipError_t yz_t(const PassArgs& a, hipStream_t s) {
-  if constexpr (split_plane<T, N>()) {
-    using B = BigCfg<T, N>;
-    hipLaunchKernelGGL((k_yzA<T, N>), dim3(a.nslots * 2 * N * B::C), dim3(B::NT), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_yzB<T, N>), dim3(a.nslots * 2 * N * (N / 16)), dim3(256), 0, s, a);
-  } else {
+  using CC = ClassCfg<T, N>;
+  if constexpr (CC::C == 2)
     hipLaunchKernelGGL((k_yz3<T, N>), dim3(a.nslots * 2 * N * 2), dim3(Plane3Cfg<N>::NT), 0, s, a);
-  }
+  else
+    hipLaunchKernelGGL((k_yzc<T, N>), dim3(a.nslots * 2 * N * CC::C), dim3(CC::NT), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, int N>
@@ -1345,7 +1367,6 @@ bool fused_supported(int n, bool dbl) {
   return n == 8 || n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
 }
 
-bool plane_split(int n, bool dbl) { return dbl ? n > 96 : n > 128; }
 
 hipError_t launch_xfwd(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(xfwd_t, dbl, n, a, s) }
 hipError_t launch_xinv(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(xinv_t, dbl, n, a, s) }

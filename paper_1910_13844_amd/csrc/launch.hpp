@@ -5,9 +5,6 @@
 namespace ls {
 
 bool fused_supported(int n, bool dbl);
-// True where the (y,z) pass runs as two kernels around a [kx][ky][z] spectrum; k_xinv then reads
-// the combined spectrum from V_SPEC instead of the two ky-parity halves.
-bool plane_split(int n, bool dbl);
 
 // x-forward pass, (y,z) convolution, x-inverse pass, far-field passes.
 hipError_t launch_xfwd(bool dbl, int n, const PassArgs& a, hipStream_t s);
