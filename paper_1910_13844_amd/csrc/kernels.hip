@@ -40,6 +40,14 @@ __device__ __forceinline__ void stv(void* p, size_t i, cplx<T> v) {
 }
 template <typename T>
 __device__ __forceinline__ T ldr(const void* p, size_t i) { return ((const LS_GLOBAL T*)p)[i]; }
+// Load at a 32-bit byte offset from a base that is uniform across the wavefront: the address
+// is formed by the memory instruction (scalar base + vector offset), with no 64-bit vector
+// arithmetic per load.
+template <typename T>
+__device__ __forceinline__ cplx<T> ldo(const void* base, uint32_t boff) {
+  const LS_GLOBAL T* q = (const LS_GLOBAL T*)((const LS_GLOBAL char*)base + boff);
+  return cplx<T>{q[0], q[1]};
+}
 
 __device__ __forceinline__ bool slot_active(const PassArgs& a, int slot) {
   return (a.mask >> a.st[slot].status) & 1u;
@@ -158,6 +166,12 @@ constexpr int row_lanes() {
     return Split<N>::L;
   else
     return Lanes<N>::value;
+}
+
+constexpr int largest_divisor_upto(int n, int cap) {
+  int d = cap < n ? cap : n;
+  while (n % d) --d;
+  return d;
 }
 
 template <int N>
@@ -324,59 +338,67 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   const SlotDesc& d = a.desc[slot];
   for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
   {
-    constexpr int CB = (CL > 1 && sizeof(T) == 4 && IT2 <= 16) ? 2 : 1;  // classes per batch of loads
-    static_assert(CL == 1 || (CM % TY == 0 && CL % CB == 0), "y tiles must stay inside one period");
+    static_assert(CL == 1 || (CM % TY == 0 && CL % 2 == 0), "y tiles must stay inside one period");
     const void* spec = d.vec[a.spec];
     const int j0 = y0 % CM;
-    // sum_c w^c Y_c with w = exp(+i pi y / n), by Horner's rule from the last class down; the
-    // loads of CB classes are issued together
-    auto load = [&](cplx<T>(&v)[CB][IT2], int c0) {
+    // byte offset of (kx, z, j0 + yy) inside one class block; class blocks are 2n nz CM apart
+    const size_t cstride = (size_t)2 * N * a.nz * CM * sizeof(cplx<T>);
+    const uint32_t off0 = (uint32_t)(((tid / TY) * a.nz + z) * CM + j0 + tid % TY) * (uint32_t)sizeof(cplx<T>);
+    constexpr uint32_t OFF_IT = (256 / TY) * CM * sizeof(cplx<T>);  // per it: 256 / TY more kx
+    // outputs are handled in chunks of ITC per thread so that three chunk-sized register sets
+    // (sum, current class, next class) fit beside the rest of the kernel
+    constexpr int ITC = largest_divisor_upto(IT2, sizeof(T) == 4 ? 16 : 8);
+    auto load = [&](cplx<T>(&v)[ITC], int c, int it0) {
+      const char* cbase = (const char*)spec + (size_t)c * cstride;
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-        for (int it = 0; it < IT2; ++it) {
-          const int i = tid + it * 256;
-          if (i < 2 * N * TY) {
-            const size_t gi = (((size_t)(c0 + cb) * 2 * N + i / TY) * a.nz + z) * CM + j0 + i % TY;
-            v[cb][it] = ld<T>(spec, gi);
-          }
-        }
+      for (int k = 0; k < ITC; ++k) {
+        const int it = it0 + k;
+        const int i = tid + it * 256;
+        if (i < 2 * N * TY) v[k] = ldo<T>(cbase, off0 + (uint32_t)it * OFF_IT * (uint32_t)a.nz);
+      }
     };
-    cplx<T> acc[IT2];
-    {
-      cplx<T> v[CB][IT2];
-      load(v, CL - CB);
-      __syncthreads();  // tw visible
-      fill_twl_any<T, N>(twl, tw, tid, 256);
+    // sum_c w^c Y_c with w = exp(+i pi y / n), by Horner's rule from the last class down; the
+    // loads of the next class are in flight while the current one is accumulated
+#pragma unroll 1
+    for (int it0 = 0; it0 < IT2; it0 += ITC) {
+      cplx<T> acc[ITC];
+      if constexpr (CL == 1) {
+        load(acc, 0, it0);
+        if (it0 == 0) {
+          __syncthreads();  // tw visible
+          fill_twl_any<T, N>(twl, tw, tid, 256);
+        }
+      } else {
+        cplx<T> va[ITC], vb[ITC];
+        load(va, CL - 1, it0);
+        load(vb, CL - 2, it0);
+        if (it0 == 0) {
+          __syncthreads();  // tw visible
+          fill_twl_any<T, N>(twl, tw, tid, 256);
+        }
+        const cplx<T> wy = conj(tw[y0 + tid % TY]);
 #pragma unroll
-      for (int it = 0; it < IT2; ++it) acc[it] = v[CB - 1][it];
-      if constexpr (CB > 1) {
-        const cplx<T> w = conj(tw[y0 + tid % TY]);
+        for (int k = 0; k < ITC; ++k) acc[k] = va[k];
+#pragma unroll 1
+        for (int c = CL - 2; c >= 2; c -= 2) {
+          load(va, c - 1, it0);
 #pragma unroll
-        for (int cb = CB - 2; cb >= 0; --cb)
+          for (int k = 0; k < ITC; ++k) acc[k] = acc[k] * wy + vb[k];
+          load(vb, c - 2, it0);
 #pragma unroll
-          for (int it = 0; it < IT2; ++it) acc[it] = acc[it] * w + v[cb][it];
+          for (int k = 0; k < ITC; ++k) acc[k] = acc[k] * wy + va[k];
+        }
+#pragma unroll
+        for (int k = 0; k < ITC; ++k) acc[k] = acc[k] * wy + vb[k];
       }
-    }
-    if constexpr (CL > CB) {
-      const cplx<T> w = conj(tw[y0 + tid % TY]);
-#pragma unroll(CL / CB <= 2 ? 2 : 1)
-      for (int c0 = CL - 2 * CB; c0 >= 0; c0 -= CB) {
-        cplx<T> v[CB][IT2];
-        load(v, c0);
 #pragma unroll
-        for (int cb = CB - 1; cb >= 0; --cb)
-#pragma unroll
-          for (int it = 0; it < IT2; ++it) acc[it] = acc[it] * w + v[cb][it];
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT2; ++it) {
-      const int i = tid + it * 256;
-      if (i < 2 * N * TY) {
-        const int yy = i % TY;
-        const int kx = i / TY;
-        ((kx & 1) ? bufO : bufE)[yy * PITCH + spec_pos<N>(kx >> 1)] = acc[it];
+      for (int k = 0; k < ITC; ++k) {
+        const int i = tid + (it0 + k) * 256;
+        if (i < 2 * N * TY) {
+          const int yy = i % TY;
+          const int kx = i / TY;
+          ((kx & 1) ? bufO : bufE)[yy * PITCH + spec_pos<N>(kx >> 1)] = acc[k];
+        }
       }
     }
   }
@@ -801,7 +823,7 @@ __device__ __forceinline__ void fill_twl_stride(cplx<T>* twl, const cplx<T>* tw,
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_yzc(PassArgs a) {
+__global__ __launch_bounds__((ClassCfg<T, N>::NT)) void k_yzc(PassArgs a) {
   using CC = ClassCfg<T, N>;
   constexpr int C = CC::C, M = CC::M, F = N / M, NT = CC::NT, PITCH = CC::PITCH;
   constexpr int LM = Split<M>::L;
@@ -827,6 +849,7 @@ __global__ __launch_bounds__(256) void k_yzc(PassArgs a) {
   const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
   // fold, with the loads of a chunk issued together
   {
+    const char* plane0 = (const char*)Sv + soff * sizeof(cplx<T>);
     constexpr int PER = N * M / NT;
     constexpr int CH0 = 32 / F < 8 ? 32 / F : 8;  // at most 32 loads in flight per thread
     constexpr int CH = PER % CH0 == 0 ? CH0 : (PER % 4 == 0 ? 4 : (PER % 2 == 0 ? 2 : 1));
@@ -840,7 +863,8 @@ __global__ __launch_bounds__(256) void k_yzc(PassArgs a) {
         const int idx = tid + (k0 + k) * NT;
         const int zz = idx / M, j = idx - zz * M;
 #pragma unroll
-        for (int m = 0; m < F; ++m) xv[k][m] = ld<T>(Sv, soff + (size_t)zz * N + j + m * M);
+        for (int m = 0; m < F; ++m)
+          xv[k][m] = ldo<T>(plane0, (uint32_t)(zz * N + j + m * M) * (uint32_t)sizeof(cplx<T>));
       }
       if (k0 == 0) __syncthreads();  // tw visible
 #pragma unroll
