@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Dict, Tuple
+from typing import List, Dict, Tuple
 
 import numpy as np
 
@@ -162,3 +162,9 @@ def random_field(seed: int, shape, complex_: bool = True) -> np.ndarray:
     if complex_:
         return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     return rng.standard_normal(shape)
+
+
+def view_subsets(Q: int, size: int, iters: int, seed: int) -> List[List[int]]:
+    """Seeded view subsets for stochastic reconstruction: `size` distinct views per iteration, sorted."""
+    rng = np.random.default_rng(seed)
+    return [sorted(rng.choice(Q, size=size, replace=False).tolist()) for _ in range(iters)]
