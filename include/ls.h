@@ -95,6 +95,7 @@ void ls_ctx_destroy(ls_ctx* ctx);
 #define LS_OP_FARFIELD 1 /* ls_farfield, ls_farfield_adj */
 #define LS_OP_GRAD 2     /* ls_grad, ls_vjp */
 #define LS_OP_APPLY 3    /* ls_apply_G, ls_apply_A */
+#define LS_OP_PROX 4     /* ls_prox_tv, ls_tv_value (Q is ignored) */
 /* Workspace needed to process Q illuminations of operation `op` in one group.  Calls accept any
  * workspace that fits at least one illumination and process the batch in groups. */
 int ls_workspace_bytes(const ls_ctx* ctx, int32_t Q, int32_t op, size_t* bytes);
@@ -170,6 +171,24 @@ int ls_batch_step(ls_batch* b, int32_t iters, void* stream);
 int ls_batch_poll(const ls_batch* b, int32_t* state, ls_solve_info* info);
 int ls_batch_release(ls_batch* b, int32_t slot);
 void ls_batch_destroy(ls_batch* b);
+
+/* Reconstruction step (Algorithm 1, Section "Optimization").  Fields are real [N] arrays of the
+ * context's precision (float for LS_C64, double for LS_C128), device memory owned by the caller.
+ *
+ * ls_prox_tv: x = prox of lam TV + i_{>=0} at z = v - gamma d (d may be NULL: z = v), i.e.
+ *   argmin_x 1/2 ||x - z||^2 + lam TV(x) (+ indicator of x >= 0 when nonneg != 0),
+ * with TV isotropic over forward differences (zero across the far faces of the grid), by `iters`
+ * steps of fast gradient projection on the dual (step 1/(12 lam)); lam = 0 or iters = 0 give the
+ * projection of z.  For the prox step of Algorithm 1 pass lam = gamma_k tau.  x may alias v or d.
+ * ws >= ls_workspace_bytes(ctx, 1, LS_OP_PROX).  Errors: LS_ERR_ARG (null pointer, negative or
+ * non-finite lam, non-finite gamma, iters < 0), LS_ERR_WORKSPACE.
+ * ls_fbs_extrapolate: v_out = f + beta (f - f_prev), the extrapolation of Algorithm 1 with
+ *   beta = (a_k - 1) / a_{k+1}; v_out may alias f or f_prev.
+ * ls_tv_value: [host] out = TV(x), accumulated in FP64 in a fixed order; synchronises `stream`. */
+int ls_prox_tv(const ls_ctx* ctx, const void* v, const void* d, double gamma, double lam, int32_t iters,
+               int32_t nonneg, void* x, void* ws, size_t ws_bytes, void* stream);
+int ls_fbs_extrapolate(const ls_ctx* ctx, const void* f, const void* f_prev, double beta, void* v_out, void* stream);
+int ls_tv_value(const ls_ctx* ctx, const void* x, double* out, void* ws, size_t ws_bytes, void* stream);
 
 /* Timing hook: enqueues `reps` launches of one pass of the solver iteration over Q slots of a
  * LS_OP_FORWARD workspace, so a single kernel can be timed in isolation (the computation of the

@@ -201,6 +201,37 @@ class Context:
                                             int(bool(accumulate)), _stream(stream)), "ls_grad_accumulate")
         return grad
 
+    # ---- reconstruction step (Algorithm 1)
+    def ls_prox_tv(self, v: torch.Tensor, lam: float, iters: int, d: Optional[torch.Tensor] = None,
+                   gamma: float = 0.0, nonneg: bool = True, out: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """prox of lam TV + i_{>=0} at v - gamma d (at v when d is None)."""
+        v = self._chk_f(v)
+        if d is not None:
+            d = self._chk_f(d)
+        x = torch.empty_like(v) if out is None else self._chk_f(out)
+        ws = self.workspace(1, L.LS_OP_PROX) if ws is None else ws
+        L.check(self.lib.ls_prox_tv(self.h, _ptr(v), _ptr(d), float(gamma), float(lam), int(iters), int(bool(nonneg)),
+                                    _ptr(x), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "ls_prox_tv")
+        return x
+
+    def ls_fbs_extrapolate(self, f: torch.Tensor, f_prev: torch.Tensor, beta: float,
+                           out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """f + beta (f - f_prev)."""
+        f, f_prev = self._chk_f(f), self._chk_f(f_prev)
+        v = torch.empty_like(f) if out is None else self._chk_f(out)
+        L.check(self.lib.ls_fbs_extrapolate(self.h, _ptr(f), _ptr(f_prev), float(beta), _ptr(v), _stream(stream)),
+                "ls_fbs_extrapolate")
+        return v
+
+    def ls_tv_value(self, x: torch.Tensor, ws: Optional[torch.Tensor] = None, stream=None) -> float:
+        x = self._chk_f(x)
+        ws = self.workspace(1, L.LS_OP_PROX) if ws is None else ws
+        out = C.c_double()
+        L.check(self.lib.ls_tv_value(self.h, _ptr(x), C.byref(out), _ptr(ws), ws.numel() * ws.element_size(),
+                                     _stream(stream)), "ls_tv_value")
+        return out.value
+
 
 def profile_pass(ctx: "Context", f: torch.Tensor, u: torch.Tensor, pass_id: int, reps: int,
                  ws: torch.Tensor, stream=None) -> None:

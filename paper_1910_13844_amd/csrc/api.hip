@@ -410,9 +410,73 @@ int ls_green_init(const ls_geom* g, void* kbuf, size_t kbuf_bytes, void* ws, siz
 
 void ls_ctx_destroy(ls_ctx* ctx) { delete ctx; }
 
+// Reconstruction-step workspace: z, x_r (N reals each), p, r (3 N reals each), TV partial sums.
+struct ProxLayout {
+  size_t z, xr, p, r, part, total;
+};
+static ProxLayout prox_layout(const ls_ctx* c) {
+  const size_t rsz = c->dbl ? 8 : 4;
+  ProxLayout L;
+  size_t o = 0;
+  L.z = o;
+  o += al(c->N * rsz);
+  L.xr = o;
+  o += al(c->N * rsz);
+  L.p = o;
+  o += al(3 * c->N * rsz);
+  L.r = o;
+  o += al(3 * c->N * rsz);
+  L.part = o;
+  o += al(((size_t)tv_partial_blocks(c->N) + 1) * sizeof(double));
+  L.total = o;
+  return L;
+}
+
 int ls_workspace_bytes(const ls_ctx* ctx, int32_t Q, int32_t op, size_t* bytes) {
-  if (check_ctx(ctx) || Q < 1 || !bytes || op < 0 || op > 3) return LS_ERR_ARG;
-  *bytes = ws_layout(ctx, Q, op).total;
+  if (check_ctx(ctx) || Q < 1 || !bytes || op < 0 || op > LS_OP_PROX) return LS_ERR_ARG;
+  *bytes = op == LS_OP_PROX ? prox_layout(ctx).total : ws_layout(ctx, Q, op).total;
+  return LS_OK;
+}
+
+int ls_prox_tv(const ls_ctx* c, const void* v, const void* d, double gamma, double lam, int32_t iters,
+               int32_t nonneg, void* x, void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !v || !x || !ws || iters < 0 || !(lam >= 0.0) || !std::isfinite(lam) || !std::isfinite(gamma))
+    return LS_ERR_ARG;
+  const ProxLayout L = prox_layout(c);
+  if (ws_bytes < L.total) return LS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  void *z = w + L.z, *xr = w + L.xr, *p = w + L.p, *r = w + L.r;
+  HIPCHK(launch_prox_init(c->dbl, v, d, gamma, z, p, r, c->N, s));
+  if (lam > 0.0 && iters > 0) {
+    double t = 1.0;
+    for (int k = 0; k < iters; ++k) {
+      HIPCHK(launch_prox_primal(c->dbl, z, r, lam, nonneg != 0, xr, c->n, s));
+      const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+      HIPCHK(launch_prox_dual(c->dbl, xr, p, r, 1.0 / (12.0 * lam), (t - 1.0) / t_next, c->n, s));
+      t = t_next;
+    }
+  }
+  // x = P_C(z - lam D^T p); p = 0 when no dual step ran
+  HIPCHK(launch_prox_primal(c->dbl, z, p, lam, nonneg != 0, x, c->n, s));
+  return LS_OK;
+}
+
+int ls_fbs_extrapolate(const ls_ctx* c, const void* f, const void* f_prev, double beta, void* v_out, void* stream) {
+  if (check_ctx(c) || !f || !f_prev || !v_out || !std::isfinite(beta)) return LS_ERR_ARG;
+  HIPCHK(launch_extrapolate(c->dbl, f, f_prev, beta, v_out, c->N, (hipStream_t)stream));
+  return LS_OK;
+}
+
+int ls_tv_value(const ls_ctx* c, const void* x, double* out, void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !x || !out || !ws) return LS_ERR_ARG;
+  const ProxLayout L = prox_layout(c);
+  if (ws_bytes < L.total) return LS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  double* part = (double*)((char*)ws + L.part);
+  const int nb = tv_partial_blocks(c->N);
+  HIPCHK(launch_tv_value(c->dbl, x, c->n, part, part + nb, s));
+  HIPCHK(hipMemcpyWithStream(out, part + nb, sizeof(double), hipMemcpyDeviceToHost, s));
   return LS_OK;
 }
 

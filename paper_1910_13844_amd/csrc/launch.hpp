@@ -26,6 +26,17 @@ hipError_t launch_convert(bool dbl, const double* src, void* dst, size_t N, hipS
 hipError_t launch_residual(bool dbl, int m, const void* y, const void* ymeas, int Q, void* r, double* stats,
                            hipStream_t s);
 
+// reconstruction step (recon.hip)
+hipError_t launch_prox_init(bool dbl, const void* v, const void* d, double gamma, void* z, void* p, void* r,
+                            size_t N, hipStream_t s);
+hipError_t launch_prox_primal(bool dbl, const void* b, const void* q, double lam, int nonneg, void* x, int n,
+                              hipStream_t s);
+hipError_t launch_prox_dual(bool dbl, const void* x, void* p, void* r, double step, double beta, int n, hipStream_t s);
+hipError_t launch_extrapolate(bool dbl, const void* f, const void* fp, double beta, void* out, size_t N,
+                              hipStream_t s);
+hipError_t launch_tv_value(bool dbl, const void* x, int n, double* part, double* out, hipStream_t s);
+int tv_partial_blocks(size_t N);
+
 inline int ty_of(int n) { return n < 16 ? n : 16; }
 inline int blocks_per_slot(int n, int nz) { return nz * (n / ty_of(n)); }
 
