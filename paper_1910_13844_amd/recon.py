@@ -54,6 +54,29 @@ def reconstruct(ctx: Context, dirs, y_meas: torch.Tensor, f0: torch.Tensor, tau:
     return f_prev
 
 
+def lipschitz_estimate(ctx: Context, dirs, y_meas: torch.Tensor, f0: torch.Tensor, iters: int = 8,
+                       seed: int = 0) -> float:
+    """Largest eigenvalue of sum_q Re(J_q^* J_q) / ||y_q||^2 at f0 = 0 by power iteration (the
+    Lipschitz constant of the data-term gradient of the linearised model).  Algorithm 1 leaves
+    gamma_0 free; 1 / L scaled to the subset size is the default step of ``main``.  J_q df is the far
+    field of df . u_in,q (ls_farfield) and J_q^* r one adjoint solve (ls_vjp), both at f0 = 0
+    where the solves are the identity."""
+    dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    zero = torch.zeros_like(f0)
+    u, _ = ctx.ls_forward(zero, dirs, tol=1e-6)
+    w = (y_meas.abs() ** 2).sum(dim=(1, 2)).to(ctx.cdtype).reshape(-1, 1, 1)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    x = torch.rand(f0.shape, generator=g, dtype=torch.float64).to(f0.device, f0.dtype)
+    lam = 0.0
+    for _ in range(iters):
+        x = x / x.norm()
+        jx = ctx.ls_farfield(x, u)
+        hx, _ = ctx.ls_vjp(zero, u, (jx / w).contiguous(), tol=1e-6)
+        lam = float((hx * x).sum())
+        x = hx
+    return lam
+
+
 def main(argv=None) -> int:
     """Reconstruct the gradient workload's perturbed phantom from its simulated measurements."""
     from . import workloads
@@ -64,7 +87,8 @@ def main(argv=None) -> int:
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--subset", type=int, default=8)
     ap.add_argument("--tau", type=float, default=1e-4)
-    ap.add_argument("--gamma0", type=float, default=30.0)
+    ap.add_argument("--gamma0", type=float, default=None,
+                    help="initial step; default 1 / L of the subset's linearised data term")
     ap.add_argument("--tv-iters", type=int, default=50)
     ap.add_argument("--prec", default="c64")
     args = ap.parse_args(argv)
@@ -78,16 +102,21 @@ def main(argv=None) -> int:
     y = torch.from_numpy(workloads.add_noise(ctx.ls_farfield(ft, u).cpu().numpy())).to(dev, ctx.cdtype)
     del u
     subs = workloads.view_subsets(Q, args.subset, args.iters, seed=7)
+    f_start = torch.zeros_like(ft)
+    L_full = lipschitz_estimate(ctx, dirs, y, f_start)
+    gamma0 = args.gamma0 if args.gamma0 is not None else Q / (args.subset * L_full)
     hist: List[dict] = []
     torch.cuda.synchronize()
     t = time.perf_counter()
-    f = reconstruct(ctx, dirs, y, torch.zeros_like(ft), args.tau, args.gamma0, subs, args.tv_iters, history=hist)
+    f = reconstruct(ctx, dirs, y, f_start, args.tau, gamma0, subs, args.tv_iters, history=hist)
     torch.cuda.synchronize()
     total = time.perf_counter() - t
     err = float((f - ft).norm() / ft.norm())
-    print(json.dumps({"n": n, "views": Q, "iters": args.iters, "subset": args.subset, "seconds": total,
+    print(json.dumps({"n": n, "views": Q, "iters": args.iters, "subset": args.subset, "lipschitz": L_full,
+                      "gamma0": gamma0, "tau": args.tau, "tv_iters": args.tv_iters, "seconds": total,
                       "seconds_per_iter": total / args.iters, "rel_err_to_truth": err,
-                      "loss_at_v": [h["loss_at_v"] for h in hist]}), flush=True)
+                      "loss_at_v": [h["loss_at_v"] for h in hist],
+                      "solver_iters_mean": [float(np.mean(h["iters"])) for h in hist]}), flush=True)
     return 0
 
 
