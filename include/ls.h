@@ -96,6 +96,7 @@ void ls_ctx_destroy(ls_ctx* ctx);
 #define LS_OP_GRAD 2     /* ls_grad, ls_vjp */
 #define LS_OP_APPLY 3    /* ls_apply_G, ls_apply_A */
 #define LS_OP_PROX 4     /* ls_prox_tv, ls_tv_value (Q is ignored) */
+#define LS_OP_INCIDENT 5 /* ls_incident_field */
 /* Workspace needed to process Q illuminations of operation `op` in one group.  Calls accept any
  * workspace that fits at least one illumination and process the batch in groups. */
 int ls_workspace_bytes(const ls_ctx* ctx, int32_t Q, int32_t op, size_t* bytes);
@@ -171,6 +172,23 @@ int ls_batch_step(ls_batch* b, int32_t iters, void* stream);
 int ls_batch_poll(const ls_batch* b, int32_t* state, ls_solve_info* info);
 int ls_batch_release(ls_batch* b, int32_t slot);
 void ls_batch_destroy(ls_batch* b);
+
+/* Incident fields from measured detector fields (Section "Computation of the 3D Incident Field",
+ * angular spectrum with tilt transfer).  y_in: device [Q][n][n] complex (field precision), the field
+ * on the detector plane x3 = x_Gamma sampled on the lateral voxel grid ([y][x], positions i - n/2 + 1).
+ * ktilde: [host] Q x 2 lateral wave-vector components (k~_x, k~_y) in radians per voxel, read when
+ * tilt != 0.  uin: out [Q][N].  For each slice z: u_in = exp(i x~.k~) IDFT2( DFT2(y_in exp(-i x~.k~))
+ * exp(-i (x_Gamma - z) sqrt(kbh^2 - |w + k~|^2)) ), periodic 2D DFTs over the n x n grid, evanescent
+ * components (|w + k~| > kbh) dropped; tilt = 0 propagates y_in itself (k~ = 0).  FP64 throughout,
+ * rounded once.  ws >= ls_workspace_bytes(ctx, Qg, LS_OP_INCIDENT) for some group Qg >= 1 (the call
+ * processes the batch in groups).  Errors: LS_ERR_ARG (null pointers, non-finite tilt),
+ * LS_ERR_WORKSPACE. */
+int ls_incident_field(const ls_ctx* ctx, const void* y_in, const double* ktilde, int32_t Q, int32_t tilt, void* uin,
+                      void* ws, size_t ws_bytes, void* stream);
+/* Forward solve, eq. (lipp1), with stored incident fields: as ls_forward with b = x0 = uin[q]
+ * (device [Q][N], e.g. from ls_incident_field) instead of plane waves.  uin must not alias u. */
+int ls_forward_uin(const ls_ctx* ctx, const void* f, int32_t Q, const void* uin, void* u, const ls_solve_opts* opts,
+                   ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* Reconstruction step (Algorithm 1, Section "Optimization").  Fields are real [N] arrays of the
  * context's precision (float for LS_C64, double for LS_C128), device memory owned by the caller.

@@ -13,7 +13,7 @@ LIB_PATH = os.environ.get("LS_LIBRARY", os.path.join(HERE, "libls.so"))
 
 LS_C64 = 0
 LS_C128 = 1
-LS_OP_FORWARD, LS_OP_FARFIELD, LS_OP_GRAD, LS_OP_APPLY, LS_OP_PROX = 0, 1, 2, 3, 4
+LS_OP_FORWARD, LS_OP_FARFIELD, LS_OP_GRAD, LS_OP_APPLY, LS_OP_PROX, LS_OP_INCIDENT = 0, 1, 2, 3, 4, 5
 
 # every symbol declared in include/ls.h
 EXPORTS = [
@@ -22,6 +22,7 @@ EXPORTS = [
     "ls_farfield_adj", "ls_vjp", "ls_grad", "ls_batch_bytes", "ls_batch_create", "ls_batch_admit",
     "ls_batch_step", "ls_batch_poll", "ls_batch_release", "ls_batch_destroy", "ls_profile_pass",
     "ls_residual", "ls_grad_accumulate", "ls_prox_tv", "ls_fbs_extrapolate", "ls_tv_value",
+    "ls_incident_field", "ls_forward_uin",
 ]
 
 
@@ -87,6 +88,8 @@ def load() -> C.CDLL:
         "ls_prox_tv": (C.c_int, [vp, vp, vp, C.c_double, C.c_double, i32, i32, vp, vp, sz, vp]),
         "ls_fbs_extrapolate": (C.c_int, [vp, vp, vp, C.c_double, vp, vp]),
         "ls_tv_value": (C.c_int, [vp, vp, dp, vp, sz, vp]),
+        "ls_incident_field": (C.c_int, [vp, vp, dp, i32, i32, vp, vp, sz, vp]),
+        "ls_forward_uin": (C.c_int, [vp, vp, i32, vp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

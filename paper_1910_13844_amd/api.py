@@ -128,6 +128,40 @@ class Context:
                                     C.byref(o), info, _ptr(ws), ws.numel(), _stream(stream)), "ls_forward")
         return u, [i.as_dict() for i in info]
 
+    def ls_forward_uin(self, f: torch.Tensor, uin: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
+                       max_restarts: int = 3, u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                       stream=None) -> Tuple[torch.Tensor, List[dict]]:
+        """Forward solves with stored incident volumes uin [Q, n, n, n]."""
+        f = self._chk_f(f)
+        uin = self._chk_vol(uin, "uin")
+        Q = uin.numel() // self.N
+        if u is None:
+            u = torch.empty_like(uin)
+        self._chk_vol(u, "u")
+        ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
+        info = (L.SolveInfo * Q)()
+        o = self._opts(tol, maxit, max_restarts)
+        L.check(self.lib.ls_forward_uin(self.h, _ptr(f), Q, _ptr(uin), _ptr(u), C.byref(o), info, _ptr(ws), ws.numel(),
+                                        _stream(stream)), "ls_forward_uin")
+        return u, [i.as_dict() for i in info]
+
+    def ls_incident_field(self, y_in: torch.Tensor, ktilde=None, tilt: bool = True, out: Optional[torch.Tensor] = None,
+                          ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Incident volumes [Q, n, n, n] from detector fields y_in [Q, n, n]; ktilde [Q, 2] (x, y)."""
+        y_in = y_in.contiguous()
+        if y_in.dtype != self.cdtype or y_in.device != self.device or tuple(y_in.shape[-2:]) != (self.n, self.n):
+            raise ValueError(f"y_in: expected {self.cdtype} [Q, {self.n}, {self.n}] on {self.device}")
+        Q = y_in.numel() // (self.n * self.n)
+        kt = np.ascontiguousarray(np.zeros((Q, 2)) if ktilde is None else np.asarray(ktilde, dtype=np.float64)
+                                  .reshape(Q, 2))
+        u = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device) if out is None else out
+        self._chk_vol(u, "out")
+        ws = self.workspace(Q, L.LS_OP_INCIDENT) if ws is None else ws
+        L.check(self.lib.ls_incident_field(self.h, _ptr(y_in), kt.ctypes.data_as(C.POINTER(C.c_double)), Q,
+                                           int(bool(tilt)), _ptr(u), _ptr(ws), ws.numel(), _stream(stream)),
+                "ls_incident_field")
+        return u
+
     def ls_farfield(self, f: torch.Tensor, u: torch.Tensor, ws: Optional[torch.Tensor] = None, stream=None
                     ) -> torch.Tensor:
         f = self._chk_f(f)

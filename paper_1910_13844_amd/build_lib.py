@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libls.so")
-SOURCES = ["kernels.hip", "green.hip", "recon.hip", "api.hip"]
+SOURCES = ["kernels.hip", "green.hip", "recon.hip", "incident.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LS_OFFLOAD_ARCH", "gfx950")
 

@@ -432,9 +432,69 @@ static ProxLayout prox_layout(const ls_ctx* c) {
   return L;
 }
 
+// Incident-field workspace for Q illuminations: FP64 twiddles (n), tilts (2 Q), detector
+// spectra (Q n^2) and propagated slices (Q n^3).
+struct IncLayout {
+  size_t tw, kt, A, B, total;
+};
+static IncLayout inc_layout(const ls_ctx* c, int Q) {
+  IncLayout L;
+  const size_t n = c->n, cz = 2 * sizeof(double);
+  size_t o = 0;
+  L.tw = o;
+  o += al(n * cz);
+  L.kt = o;
+  o += al(2 * (size_t)Q * sizeof(double));
+  L.A = o;
+  o += al((size_t)Q * n * n * cz);
+  L.B = o;
+  o += al((size_t)Q * n * n * n * cz);
+  L.total = o;
+  return L;
+}
+
 int ls_workspace_bytes(const ls_ctx* ctx, int32_t Q, int32_t op, size_t* bytes) {
-  if (check_ctx(ctx) || Q < 1 || !bytes || op < 0 || op > LS_OP_PROX) return LS_ERR_ARG;
-  *bytes = op == LS_OP_PROX ? prox_layout(ctx).total : ws_layout(ctx, Q, op).total;
+  if (check_ctx(ctx) || Q < 1 || !bytes || op < 0 || op > LS_OP_INCIDENT) return LS_ERR_ARG;
+  if (op == LS_OP_PROX)
+    *bytes = prox_layout(ctx).total;
+  else if (op == LS_OP_INCIDENT)
+    *bytes = inc_layout(ctx, Q).total;
+  else
+    *bytes = ws_layout(ctx, Q, op).total;
+  return LS_OK;
+}
+
+int ls_incident_field(const ls_ctx* c, const void* y_in, const double* ktilde, int32_t Q, int32_t tilt, void* uin,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !y_in || !uin || !ws || Q < 1 || (tilt && !ktilde)) return LS_ERR_ARG;
+  if (tilt)
+    for (int i = 0; i < 2 * Q; ++i)
+      if (!std::isfinite(ktilde[i])) return LS_ERR_ARG;
+  int Qg = 0;
+  for (int q = Q; q >= 1 && !Qg; q = q > 1 ? q / 2 : 0)
+    if (inc_layout(c, q).total <= ws_bytes) Qg = q;
+  if (Qg < 1) return LS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const int n = c->n;
+  std::vector<double> tw;
+  twiddles(n, tw);
+  const IncLayout L = inc_layout(c, Qg);
+  HIPCHK(hipMemcpyWithStream(w + L.tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  const size_t M = (size_t)n * n;
+  for (int q0 = 0; q0 < Q; q0 += Qg) {
+    const int nq = std::min(Qg, Q - q0);
+    double* kt = (double*)(w + L.kt);
+    if (tilt) HIPCHK(hipMemcpyWithStream(kt, ktilde + 2 * q0, 2 * nq * sizeof(double), hipMemcpyHostToDevice, s));
+    cplx<double>* A = (cplx<double>*)(w + L.A);
+    cplx<double>* B = (cplx<double>*)(w + L.B);
+    const cplx<double>* twd = (const cplx<double>*)(w + L.tw);
+    HIPCHK(launch_inc_demod(c->dbl, (const char*)y_in + (size_t)q0 * M * c->csz, kt, tilt != 0, A, n, nq, s));
+    HIPCHK(fft2_batched(n, -1, A, nq, twd, s));
+    HIPCHK(launch_inc_prop(A, kt, tilt != 0, c->g.kbh, c->g.xg, B, n, nq, s));
+    HIPCHK(fft2_batched(n, +1, B, nq * n, twd, s));
+    HIPCHK(launch_inc_mod(c->dbl, B, kt, tilt != 0, (char*)uin + (size_t)q0 * M * n * c->csz, n, nq, s));
+  }
   return LS_OK;
 }
 
@@ -521,9 +581,9 @@ int ls_apply_A(const ls_ctx* ctx, const void* f, const void* v, void* out, int32
   return apply_common(ctx, f, v, out, Q, ws, ws_bytes, stream, true);
 }
 
-int ls_forward(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, void* u, const ls_solve_opts* opts,
-               ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
-  if (check_ctx(c) || !f || !dirs || !u || !ws || Q < 1) return LS_ERR_ARG;
+// Forward solves with plane-wave (dirs) or stored (uin) incident fields.
+static int forward_common(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, const void* uin, void* u,
+                          const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   const ls_solve_opts o = opts_or_default(opts);
   if (!opts_ok(o)) return LS_ERR_ARG;
   const int Qg = fit_slots(c, Q, LS_OP_FORWARD, ws_bytes);
@@ -540,7 +600,10 @@ int ls_forward(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, vo
       d[i] = blank_desc(c, f);
       d[i].vec[V_X] = (char*)u + (size_t)(q0 + i) * c->N * c->csz;
       bind_solver(c, w, L, i, 0, d[i]);
-      for (int j = 0; j < 3; ++j) d[i].d[j] = dirs[3 * (q0 + i) + j];
+      if (uin)
+        d[i].vec[V_B] = (void*)((const char*)uin + (size_t)(q0 + i) * c->N * c->csz);
+      else
+        for (int j = 0; j < 3; ++j) d[i].d[j] = dirs[3 * (q0 + i) + j];
     }
     Run r = make_run(c, w, L, nq, 0, s);
     int rc = upload(r, d, &st);
@@ -550,6 +613,18 @@ int ls_forward(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, vo
       for (int i = 0; i < nq; ++i) to_info(h[i], info + q0 + i);
   }
   return LS_OK;
+}
+
+int ls_forward(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, void* u, const ls_solve_opts* opts,
+               ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !f || !dirs || !u || !ws || Q < 1) return LS_ERR_ARG;
+  return forward_common(c, f, Q, dirs, nullptr, u, opts, info, ws, ws_bytes, stream);
+}
+
+int ls_forward_uin(const ls_ctx* c, const void* f, int32_t Q, const void* uin, void* u, const ls_solve_opts* opts,
+                   ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !f || !uin || !u || !ws || Q < 1 || uin == u) return LS_ERR_ARG;
+  return forward_common(c, f, Q, nullptr, uin, u, opts, info, ws, ws_bytes, stream);
 }
 
 int ls_farfield(const ls_ctx* c, const void* f, const void* u, int32_t Q, void* y, void* ws, size_t ws_bytes,

@@ -178,7 +178,7 @@ template <int M, int DIR>
 static hipError_t fft3_t(cplx<double>* d, const cplx<double>* tw, hipStream_t s) {
   constexpr int L = Lanes<M>::value;
   constexpr int NG = 256 / L;
-  constexpr int TX = M >= 384 ? 8 : 16;
+  constexpr int TX = M >= 384 ? 8 : (M < 16 ? M : 16);
   const size_t lines = (size_t)M * M;
   hipLaunchKernelGGL((k_fft_rows<M, DIR>), dim3((unsigned)((lines + NG - 1) / NG)), dim3(256), 0, s, d, lines, tw);
   // y lines: element stride M, outer (z) stride M^2
@@ -195,7 +195,7 @@ template <int M, int DIR>
 static hipError_t fft2_t(cplx<double>* d, int planes, const cplx<double>* tw, hipStream_t s) {
   constexpr int L = Lanes<M>::value;
   constexpr int NG = 256 / L;
-  constexpr int TX = M >= 384 ? 8 : 16;
+  constexpr int TX = M >= 384 ? 8 : (M < 16 ? M : 16);
   const size_t lines = (size_t)planes * M;
   hipLaunchKernelGGL((k_fft_rows<M, DIR>), dim3((unsigned)((lines + NG - 1) / NG)), dim3(256), 0, s, d, lines, tw);
   hipLaunchKernelGGL((k_fft_cols<M, DIR, TX>), dim3(planes * (M / TX)), dim3(256), 0, s, d, (size_t)M, (size_t)M * M,
@@ -226,9 +226,11 @@ static hipError_t fft2(int M, int dir, cplx<double>* d, int planes, const cplx<d
   case MM:                                                                           \
     return dir < 0 ? fft2_t<MM, -1>(d, planes, tw, s) : fft2_t<MM, +1>(d, planes, tw, s);
   switch (M) {
+    LS_F2(8)
     LS_F2(16)
     LS_F2(32)
     LS_F2(64)
+    LS_F2(96)
     LS_F2(128)
     LS_F2(192)
     LS_F2(256)
@@ -237,6 +239,10 @@ static hipError_t fft2(int M, int dir, cplx<double>* d, int planes, const cplx<d
     default: return hipErrorInvalidValue;
   }
 #undef LS_F2
+}
+
+hipError_t fft2_batched(int M, int dir, cplx<double>* d, int planes, const cplx<double>* tw, hipStream_t s) {
+  return fft2(M, dir, d, planes, tw, s);
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

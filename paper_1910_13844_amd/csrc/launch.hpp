@@ -37,6 +37,13 @@ hipError_t launch_extrapolate(bool dbl, const void* f, const void* fp, double be
 hipError_t launch_tv_value(bool dbl, const void* x, int n, double* part, double* out, hipStream_t s);
 int tv_partial_blocks(size_t N);
 
+// incident field from detector fields (incident.hip)
+hipError_t launch_inc_demod(bool dbl, const void* y, const double* kt, int tilt, void* A, int n, int Q,
+                            hipStream_t s);
+hipError_t launch_inc_prop(const void* A, const double* kt, int tilt, double k, double xg, void* B, int n, int Q,
+                           hipStream_t s);
+hipError_t launch_inc_mod(bool dbl, const void* B, const double* kt, int tilt, void* u, int n, int Q, hipStream_t s);
+
 inline int ty_of(int n) { return n < 16 ? n : 16; }
 inline int blocks_per_slot(int n, int nz) { return nz * (n / ty_of(n)); }
 
