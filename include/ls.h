@@ -190,6 +190,38 @@ int ls_incident_field(const ls_ctx* ctx, const void* y_in, const double* ktilde,
 int ls_forward_uin(const ls_ctx* ctx, const void* f, int32_t Q, const void* uin, void* u, const ls_solve_opts* opts,
                    ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* Detector-side operators of eq. (lipp2) (Sections "Green's Function Discretization for the
+ * Measurements" and "Free-Space Propagation and Pupil Function"), on m x m detector fields
+ * [Q][m][m] complex (field precision, device), pixel spacing h, grids centred (pixel a at lateral
+ * position a - m/2 + 1).  FP64 internally, rounded once.
+ * ls_detector_bytes: workspace for the calls below with this m.
+ * ls_farfield_wide: y = G~_m (f . u) on a camera of m >= n pixels (m - n even): the slice sum of
+ *   2D linear convolutions with the untruncated g, by DFTs of size M >= m + n - 1 (M from 8, 16,
+ *   32, 64, 96, 128, 192, 256, 384, 512, else LS_ERR_UNSUPPORTED).  m = n equals ls_farfield.
+ * ls_farfield_wide_adj: out [Q][N] = G~_m^T r (or G~_m^T conj(r) when conj != 0), the transpose.
+ * ls_pupil: out = crop_m IDFT_2m( p . DFT_2m(pad y) ), p(w) = 1{|w| <= na kbh} exp(i dz sqrt(kbh^2 -
+ *   |w|^2)) (ideal pupil of numerical aperture na relative to the background index, propagation
+ *   over dz voxels); adjoint != 0 applies conj(p).  2m must be one of the DFT sizes above.
+ * ls_decimate: detector sampling h' = q h: out [Q][m/q][m/q] keeps every q-th pixel (the kept set
+ *   contains the pixel at lateral position 0); transpose != 0 maps [Q][m/q][m/q] back to [Q][m][m]
+ *   with zeros elsewhere.  m % q == 0; out must not alias y.
+ * Errors: LS_ERR_ARG (null pointers, m < n or m - n odd for the far field, non-finite na/dz),
+ * LS_ERR_UNSUPPORTED (DFT size), LS_ERR_WORKSPACE. */
+int ls_detector_bytes(const ls_ctx* ctx, int32_t m, size_t* bytes);
+int ls_farfield_wide(const ls_ctx* ctx, int32_t m, const void* f, const void* u, int32_t Q, void* y, void* ws,
+                     size_t ws_bytes, void* stream);
+int ls_farfield_wide_adj(const ls_ctx* ctx, int32_t m, const void* r, int32_t conj, int32_t Q, void* out, void* ws,
+                         size_t ws_bytes, void* stream);
+int ls_pupil(const ls_ctx* ctx, int32_t m, const void* y, int32_t Q, double na, double dz, int32_t adjoint, void* out,
+             void* ws, size_t ws_bytes, void* stream);
+int ls_decimate(const ls_ctx* ctx, int32_t m, int32_t q, const void* y, int32_t Q, void* out, int32_t transpose,
+                void* stream);
+/* Gradient for a volume right-hand side (the Jacobian-adjoint step of Algorithm 1 behind any detector
+ * chain): grad [N] real = sum_q Re(u_q . w_q), (I - G diag f) w_q = b_q.  With b_q = G~^T conj(B^* gy_q)
+ * for a detector chain B this is Re(J^* gy) of the chained model.  ws as for LS_OP_GRAD. */
+int ls_vjp_rhs(const ls_ctx* ctx, const void* f, const void* u, int32_t Q, const void* b, void* grad,
+               const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
 /* Reconstruction step (Algorithm 1, Section "Optimization").  Fields are real [N] arrays of the
  * context's precision (float for LS_C64, double for LS_C128), device memory owned by the caller.
  *

@@ -22,7 +22,8 @@ EXPORTS = [
     "ls_farfield_adj", "ls_vjp", "ls_grad", "ls_batch_bytes", "ls_batch_create", "ls_batch_admit",
     "ls_batch_step", "ls_batch_poll", "ls_batch_release", "ls_batch_destroy", "ls_profile_pass",
     "ls_residual", "ls_grad_accumulate", "ls_prox_tv", "ls_fbs_extrapolate", "ls_tv_value",
-    "ls_incident_field", "ls_forward_uin",
+    "ls_incident_field", "ls_forward_uin", "ls_detector_bytes", "ls_farfield_wide", "ls_farfield_wide_adj",
+    "ls_pupil", "ls_decimate", "ls_vjp_rhs",
 ]
 
 
@@ -90,6 +91,12 @@ def load() -> C.CDLL:
         "ls_tv_value": (C.c_int, [vp, vp, dp, vp, sz, vp]),
         "ls_incident_field": (C.c_int, [vp, vp, dp, i32, i32, vp, vp, sz, vp]),
         "ls_forward_uin": (C.c_int, [vp, vp, i32, vp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
+        "ls_detector_bytes": (C.c_int, [vp, i32, P(sz)]),
+        "ls_farfield_wide": (C.c_int, [vp, i32, vp, vp, i32, vp, vp, sz, vp]),
+        "ls_farfield_wide_adj": (C.c_int, [vp, i32, vp, i32, i32, vp, vp, sz, vp]),
+        "ls_pupil": (C.c_int, [vp, i32, vp, i32, C.c_double, C.c_double, i32, vp, vp, sz, vp]),
+        "ls_decimate": (C.c_int, [vp, i32, i32, vp, i32, vp, i32, vp]),
+        "ls_vjp_rhs": (C.c_int, [vp, vp, vp, i32, vp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -235,6 +235,79 @@ class Context:
                                             int(bool(accumulate)), _stream(stream)), "ls_grad_accumulate")
         return grad
 
+    # ---- detector-side operators
+    def detector_workspace(self, m: int) -> torch.Tensor:
+        b = C.c_size_t()
+        L.check(self.lib.ls_detector_bytes(self.h, int(m), C.byref(b)), "ls_detector_bytes")
+        key = ("det", int(m))
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < b.value:
+            self._ws.pop(key, None)
+            ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def _chk_det(self, y: torch.Tensor, m: int, name: str) -> torch.Tensor:
+        if y.device != self.device or y.dtype != self.cdtype or not y.is_contiguous() or tuple(y.shape[-2:]) != (m, m):
+            raise ValueError(f"{name}: expected contiguous {self.cdtype} [..., {m}, {m}] on {self.device}")
+        return y
+
+    def ls_farfield_wide(self, m: int, f: torch.Tensor, u: torch.Tensor, stream=None) -> torch.Tensor:
+        f, u = self._chk_f(f), self._chk_vol(u, "u")
+        Q = u.numel() // self.N
+        y = torch.empty((Q, m, m), dtype=self.cdtype, device=self.device)
+        ws = self.detector_workspace(m)
+        L.check(self.lib.ls_farfield_wide(self.h, int(m), _ptr(f), _ptr(u), Q, _ptr(y), _ptr(ws), ws.numel(),
+                                          _stream(stream)), "ls_farfield_wide")
+        return y
+
+    def ls_farfield_wide_adj(self, m: int, r: torch.Tensor, conj: bool = False, stream=None) -> torch.Tensor:
+        r = self._chk_det(r.contiguous(), m, "r")
+        Q = r.numel() // (m * m)
+        out = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device)
+        ws = self.detector_workspace(m)
+        L.check(self.lib.ls_farfield_wide_adj(self.h, int(m), _ptr(r), int(bool(conj)), Q, _ptr(out), _ptr(ws),
+                                              ws.numel(), _stream(stream)), "ls_farfield_wide_adj")
+        return out
+
+    def ls_pupil(self, y: torch.Tensor, na: float, dz: float, adjoint: bool = False, stream=None) -> torch.Tensor:
+        m = y.shape[-1]
+        y = self._chk_det(y.contiguous(), m, "y")
+        Q = y.numel() // (m * m)
+        out = torch.empty_like(y)
+        ws = self.detector_workspace(m)
+        L.check(self.lib.ls_pupil(self.h, int(m), _ptr(y), Q, float(na), float(dz), int(bool(adjoint)), _ptr(out),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "ls_pupil")
+        return out
+
+    def ls_decimate(self, y: torch.Tensor, q: int, m: Optional[int] = None, transpose: bool = False,
+                    stream=None) -> torch.Tensor:
+        if not transpose:
+            m = y.shape[-1]
+            y = self._chk_det(y.contiguous(), m, "y")
+            Q = y.numel() // (m * m)
+            out = torch.empty((Q, m // q, m // q), dtype=self.cdtype, device=self.device)
+        else:
+            y = self._chk_det(y.contiguous(), m // q, "y")
+            Q = y.numel() // ((m // q) ** 2)
+            out = torch.empty((Q, m, m), dtype=self.cdtype, device=self.device)
+        L.check(self.lib.ls_decimate(self.h, int(m), int(q), _ptr(y), Q, _ptr(out), int(bool(transpose)),
+                                     _stream(stream)), "ls_decimate")
+        return out
+
+    def ls_vjp_rhs(self, f: torch.Tensor, u: torch.Tensor, b: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
+                   max_restarts: int = 3, ws: Optional[torch.Tensor] = None, stream=None
+                   ) -> Tuple[torch.Tensor, List[dict]]:
+        f, u, b = self._chk_f(f), self._chk_vol(u, "u"), self._chk_vol(b.contiguous(), "b")
+        Q = u.numel() // self.N
+        grad = torch.empty((self.n,) * 3, dtype=self.rdtype, device=self.device)
+        ws = self.workspace(Q, L.LS_OP_GRAD) if ws is None else ws
+        info = (L.SolveInfo * Q)()
+        o = self._opts(tol, maxit, max_restarts)
+        L.check(self.lib.ls_vjp_rhs(self.h, _ptr(f), _ptr(u), Q, _ptr(b), _ptr(grad), C.byref(o), info, _ptr(ws),
+                                    ws.numel(), _stream(stream)), "ls_vjp_rhs")
+        return grad, [i.as_dict() for i in info]
+
     # ---- reconstruction step (Algorithm 1)
     def ls_prox_tv(self, v: torch.Tensor, lam: float, iters: int, d: Optional[torch.Tensor] = None,
                    gamma: float = 0.0, nonneg: bool = True, out: Optional[torch.Tensor] = None,

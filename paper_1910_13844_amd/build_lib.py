@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libls.so")
-SOURCES = ["kernels.hip", "green.hip", "recon.hip", "incident.hip", "api.hip"]
+SOURCES = ["kernels.hip", "green.hip", "recon.hip", "incident.hip", "detector.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LS_OFFLOAD_ARCH", "gfx950")
 
@@ -40,7 +40,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4) -> str:
+def build(jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -56,5 +56,5 @@ def build(jobs: int = 4) -> str:
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--jobs", type=int, default=6)
     print(build(ap.parse_args().jobs))

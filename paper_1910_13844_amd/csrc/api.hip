@@ -685,8 +685,8 @@ int ls_farfield_adj(const ls_ctx* c, const void* rdet, int32_t conj, int32_t Q, 
 
 // Shared driver of ls_vjp and ls_grad.
 static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, const void* u_in,
-                       const void* gy, const void* y_meas, void* grad, double* loss, const ls_solve_opts* opts,
-                       ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+                       const void* gy, const void* y_meas, const void* rhs, void* grad, double* loss,
+                       const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   const ls_solve_opts o = opts_or_default(opts);
   if (!opts_ok(o)) return LS_ERR_ARG;
   const int Qg = fit_slots(c, Q, LS_OP_GRAD, ws_bytes);
@@ -717,7 +717,7 @@ static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* 
       dfw[i].vec[V_AUX] = det + (size_t)i * M * c->csz;
       dad[i] = blank_desc(c, f);
       dad[i].vec[V_X] = vptr(c, w, L, i, 1);
-      dad[i].vec[V_B] = vptr(c, w, L, i, 2);
+      dad[i].vec[V_B] = rhs ? (void*)((const char*)rhs + (size_t)(q0 + i) * c->N * c->csz) : vptr(c, w, L, i, 2);
       bind_solver(c, w, L, i, 3, dad[i]);
       dad[i].vec[V_AUX] = full ? (void*)(det + (size_t)i * M * c->csz)
                                : (void*)((const char*)gy + (size_t)(q0 + i) * M * c->csz);
@@ -745,8 +745,8 @@ static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* 
       for (int i = 0; i < nq; ++i) loss_acc += hs[2 * i] / (2.0 * hs[2 * i + 1]);
       if ((rc = upload(ra, dad, &st))) return rc;
     }
-    // b = G~^T conj(r): slots are in ST_INIT, the passes act on them without changing state
-    if ((rc = farfield_adj_run(ra, V_AUX, V_T, V_B, true, M_INIT))) return rc;
+    // b = G~^T conj(r) (unless given): slots are in ST_INIT, the passes act on them without changing state
+    if (!rhs && (rc = farfield_adj_run(ra, V_AUX, V_T, V_B, true, M_INIT))) return rc;
     if ((rc = solve_all(ra, h))) return rc;
     if (info) {
       ls_solve_info* base = full ? info + Q : info;
@@ -764,13 +764,161 @@ static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* 
 int ls_vjp(const ls_ctx* c, const void* f, const void* u, int32_t Q, const void* gy, void* grad,
            const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   if (check_ctx(c) || !f || !u || !gy || !grad || !ws || Q < 1) return LS_ERR_ARG;
-  return grad_driver(c, f, Q, nullptr, u, gy, nullptr, grad, nullptr, opts, info, ws, ws_bytes, stream);
+  return grad_driver(c, f, Q, nullptr, u, gy, nullptr, nullptr, grad, nullptr, opts, info, ws, ws_bytes, stream);
+}
+
+int ls_vjp_rhs(const ls_ctx* c, const void* f, const void* u, int32_t Q, const void* b, void* grad,
+               const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !f || !u || !b || !grad || !ws || Q < 1) return LS_ERR_ARG;
+  return grad_driver(c, f, Q, nullptr, u, nullptr, nullptr, b, grad, nullptr, opts, info, ws, ws_bytes, stream);
 }
 
 int ls_grad(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, const void* y_meas, void* grad,
             double* loss, const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   if (check_ctx(c) || !f || !dirs || !y_meas || !grad || !ws || Q < 1) return LS_ERR_ARG;
-  return grad_driver(c, f, Q, dirs, nullptr, nullptr, y_meas, grad, loss, opts, info, ws, ws_bytes, stream);
+  return grad_driver(c, f, Q, dirs, nullptr, nullptr, y_meas, nullptr, grad, loss, opts, info, ws, ws_bytes, stream);
+}
+
+// ---- detector-side operators
+static int det_fft_size(int need) {
+  static const int sizes[] = {8, 16, 32, 64, 96, 128, 192, 256, 384, 512};
+  for (int v : sizes)
+    if (v >= need) return v;
+  return 0;
+}
+static const int kDetSizes[] = {8, 16, 32, 64, 96, 128, 192, 256, 384, 512};
+static bool det_size_ok(int M) {
+  for (int v : kDetSizes)
+    if (v == M) return true;
+  return false;
+}
+
+// wide far field / its transpose: tw (M), K^ (n M^2), V (n M^2), Y (M^2); pupil: tw (2m), planes
+struct DetLayout {
+  size_t tw, K, V, Y, total;
+};
+static DetLayout det_layout(const ls_ctx* c, int M) {
+  DetLayout L;
+  const size_t cz = 2 * sizeof(double), MM = (size_t)M * M;
+  size_t o = 0;
+  L.tw = o;
+  o += al((size_t)M * cz);
+  L.K = o;
+  o += al((size_t)c->n * MM * cz);
+  L.V = o;
+  o += al((size_t)c->n * MM * cz);
+  L.Y = o;
+  o += al(MM * cz);
+  L.total = o;
+  return L;
+}
+
+static hipError_t upload_twiddles(int M, void* dst, hipStream_t s) {
+  std::vector<double> tw;
+  twiddles(M, tw);
+  return hipMemcpyWithStream(dst, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice, s);
+}
+
+int ls_detector_bytes(const ls_ctx* c, int32_t m, size_t* bytes) {
+  if (check_ctx(c) || !bytes || m < 1) return LS_ERR_ARG;
+  size_t b = 0;
+  if (m >= c->n && (m - c->n) % 2 == 0) {
+    const int M = det_fft_size(m + c->n - 1);
+    if (M) b = det_layout(c, M).total;
+  }
+  const size_t pb = al(2 * (size_t)m * 2 * sizeof(double)) + al(4 * (size_t)m * m * 2 * sizeof(double));
+  *bytes = std::max(b, pb);
+  return LS_OK;
+}
+
+static int wide_check(const ls_ctx* c, int m, int& M) {
+  if (m < c->n || (m - c->n) % 2) return LS_ERR_ARG;
+  M = det_fft_size(m + c->n - 1);
+  return M ? LS_OK : LS_ERR_UNSUPPORTED;
+}
+
+int ls_farfield_wide(const ls_ctx* c, int32_t m, const void* f, const void* u, int32_t Q, void* y, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !f || !u || !y || !ws || Q < 1) return LS_ERR_ARG;
+  int M, rc;
+  if ((rc = wide_check(c, m, M))) return rc;
+  const DetLayout L = det_layout(c, M);
+  if (ws_bytes < L.total) return LS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  cplx<double>* tw = (cplx<double>*)(w + L.tw);
+  HIPCHK(upload_twiddles(M, tw, s));
+  HIPCHK(launch_det_kernel(w + L.K, c->n, M, (m - c->n) / 2, c->g.kbh, c->g.xg, s));
+  HIPCHK(fft2_batched(M, -1, (cplx<double>*)(w + L.K), c->n, tw, s));
+  const size_t mm = (size_t)m * m;
+  for (int q = 0; q < Q; ++q) {
+    HIPCHK(launch_det_pad_vol(c->dbl, f, (const char*)u + (size_t)q * c->N * c->csz, w + L.V, c->n, M, s));
+    HIPCHK(fft2_batched(M, -1, (cplx<double>*)(w + L.V), c->n, tw, s));
+    HIPCHK(launch_det_mulsum(w + L.K, w + L.V, w + L.Y, c->n, M, s));
+    HIPCHK(fft2_batched(M, +1, (cplx<double>*)(w + L.Y), 1, tw, s));
+    HIPCHK(launch_det_crop(c->dbl, w + L.Y, (char*)y + (size_t)q * mm * c->csz, m, M, 1, 1.0 / ((double)M * M), s));
+  }
+  return LS_OK;
+}
+
+int ls_farfield_wide_adj(const ls_ctx* c, int32_t m, const void* r, int32_t conj, int32_t Q, void* out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !r || !out || !ws || Q < 1) return LS_ERR_ARG;
+  int M, rc;
+  if ((rc = wide_check(c, m, M))) return rc;
+  const DetLayout L = det_layout(c, M);
+  if (ws_bytes < L.total) return LS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  cplx<double>* tw = (cplx<double>*)(w + L.tw);
+  HIPCHK(upload_twiddles(M, tw, s));
+  HIPCHK(launch_det_kernel(w + L.K, c->n, M, (m - c->n) / 2, c->g.kbh, c->g.xg, s));
+  HIPCHK(fft2_batched(M, -1, (cplx<double>*)(w + L.K), c->n, tw, s));
+  const size_t mm = (size_t)m * m;
+  for (int q = 0; q < Q; ++q) {
+    HIPCHK(launch_det_pad2(c->dbl, (const char*)r + (size_t)q * mm * c->csz, w + L.Y, m, M, 1, conj != 0, s));
+    HIPCHK(fft2_batched(M, -1, (cplx<double>*)(w + L.Y), 1, tw, s));
+    HIPCHK(launch_det_mulT(w + L.K, w + L.Y, w + L.V, c->n, M, s));
+    HIPCHK(fft2_batched(M, +1, (cplx<double>*)(w + L.V), c->n, tw, s));
+    HIPCHK(launch_det_crop(c->dbl, w + L.V, (char*)out + (size_t)q * c->N * c->csz, c->n, M, c->n,
+                           1.0 / ((double)M * M), s));
+  }
+  return LS_OK;
+}
+
+int ls_pupil(const ls_ctx* c, int32_t m, const void* y, int32_t Q, double na, double dz, int32_t adjoint, void* out,
+             void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !y || !out || !ws || Q < 1 || m < 1 || !(na >= 0.0) || !std::isfinite(na) || !std::isfinite(dz))
+    return LS_ERR_ARG;
+  const int M = 2 * m;
+  if (!det_size_ok(M)) return LS_ERR_UNSUPPORTED;
+  const size_t cz = 2 * sizeof(double), plane = (size_t)M * M * cz;
+  const size_t head = al((size_t)M * cz);
+  if (ws_bytes < head + plane) return LS_ERR_WORKSPACE;
+  const int Qg = (int)std::min<size_t>((size_t)Q, (ws_bytes - head) / plane);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  cplx<double>* tw = (cplx<double>*)w;
+  HIPCHK(upload_twiddles(M, tw, s));
+  const size_t mm = (size_t)m * m;
+  for (int q0 = 0; q0 < Q; q0 += Qg) {
+    const int nq = std::min(Qg, Q - q0);
+    cplx<double>* P = (cplx<double>*)(w + head);
+    HIPCHK(launch_det_pad2(c->dbl, (const char*)y + (size_t)q0 * mm * c->csz, P, m, M, nq, 0, s));
+    HIPCHK(fft2_batched(M, -1, P, nq, tw, s));
+    HIPCHK(launch_det_pupil(P, M, nq, c->g.kbh, na * c->g.kbh, dz, adjoint != 0, s));
+    HIPCHK(fft2_batched(M, +1, P, nq, tw, s));
+    HIPCHK(launch_det_crop(c->dbl, P, (char*)out + (size_t)q0 * mm * c->csz, m, M, nq, 1.0 / ((double)M * M), s));
+  }
+  return LS_OK;
+}
+
+int ls_decimate(const ls_ctx* c, int32_t m, int32_t q, const void* y, int32_t Q, void* out, int32_t transpose,
+                void* stream) {
+  if (check_ctx(c) || !y || !out || Q < 1 || m < 1 || q < 1 || m % q || y == out) return LS_ERR_ARG;
+  const int s0 = (m / 2 - 1) % q;
+  HIPCHK(launch_decimate(c->dbl, y, out, m, q, s0, Q, transpose != 0, (hipStream_t)stream));
+  return LS_OK;
 }
 
 int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32_t Q, int32_t reps, void* ws,

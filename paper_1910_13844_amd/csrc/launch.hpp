@@ -44,6 +44,17 @@ hipError_t launch_inc_prop(const void* A, const double* kt, int tilt, double k, 
                            hipStream_t s);
 hipError_t launch_inc_mod(bool dbl, const void* B, const double* kt, int tilt, void* u, int n, int Q, hipStream_t s);
 
+// detector-side operators (detector.hip)
+hipError_t launch_det_kernel(void* K, int n, int M, int s, double k, double xg, hipStream_t st);
+hipError_t launch_det_pad_vol(bool dbl, const void* f, const void* u, void* V, int n, int M, hipStream_t st);
+hipError_t launch_det_pad2(bool dbl, const void* y, void* P, int m, int M, int Q, int cj, hipStream_t st);
+hipError_t launch_det_mulsum(const void* K, const void* V, void* Y, int n, int M, hipStream_t st);
+hipError_t launch_det_mulT(const void* K, const void* R, void* V, int n, int M, hipStream_t st);
+hipError_t launch_det_crop(bool dbl, const void* Y, void* out, int m, int M, int Q, double scale, hipStream_t st);
+hipError_t launch_det_pupil(void* P, int M, int Q, double k, double wc, double dz, int adjoint, hipStream_t st);
+hipError_t launch_decimate(bool dbl, const void* y, void* out, int m, int q, int s, int Qn, int transpose,
+                           hipStream_t st);
+
 inline int ty_of(int n) { return n < 16 ? n : 16; }
 inline int blocks_per_slot(int n, int nz) { return nz * (n / ty_of(n)); }
 
