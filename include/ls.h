@@ -43,7 +43,7 @@ extern "C" {
 
 /* Geometry of one problem (Theorem 1, Proposition 2, Section on G~). */
 typedef struct {
-  int32_t n;    /* voxels per side; supported: 8, 16, 32, 64, 96, 128, 192, 256 (both precisions) */
+  int32_t n;    /* voxels per side; supported: 8, 16, 32, 64, 96, 128, 144, 192, 256 (both precisions) */
   int32_t p;    /* Theorem 1 padding factor, even, >= 2 (p = 4 recommended); only the 2n grid is stored */
   double kbh;   /* k_b h; must satisfy 0 < kbh < pi (Nyquist condition of Theorem 1) */
   double xg;    /* detector plane position x_Gamma / h; must exceed n/2 (plane outside Omega) */
@@ -197,7 +197,7 @@ int ls_forward_uin(const ls_ctx* ctx, const void* f, int32_t Q, const void* uin,
  * ls_detector_bytes: workspace for the calls below with this m.
  * ls_farfield_wide: y = G~_m (f . u) on a camera of m >= n pixels (m - n even): the slice sum of
  *   2D linear convolutions with the untruncated g, by DFTs of size M >= m + n - 1 (M from 8, 16,
- *   32, 64, 96, 128, 192, 256, 384, 512, else LS_ERR_UNSUPPORTED).  m = n equals ls_farfield.
+ *   32, 64, 96, 128, 144, 192, 256, 288, 384, 512, else LS_ERR_UNSUPPORTED).  m = n equals ls_farfield.
  * ls_farfield_wide_adj: out [Q][N] = G~_m^T r (or G~_m^T conj(r) when conj != 0), the transpose.
  * ls_pupil: out = crop_m IDFT_2m( p . DFT_2m(pad y) ), p(w) = 1{|w| <= na kbh} exp(i dz sqrt(kbh^2 -
  *   |w|^2)) (ideal pupil of numerical aperture na relative to the background index, propagation

@@ -781,12 +781,12 @@ int ls_grad(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, const
 
 // ---- detector-side operators
 static int det_fft_size(int need) {
-  static const int sizes[] = {8, 16, 32, 64, 96, 128, 192, 256, 384, 512};
+  static const int sizes[] = {8, 16, 32, 64, 96, 128, 144, 192, 256, 288, 384, 512};
   for (int v : sizes)
     if (v >= need) return v;
   return 0;
 }
-static const int kDetSizes[] = {8, 16, 32, 64, 96, 128, 192, 256, 384, 512};
+static const int kDetSizes[] = {8, 16, 32, 64, 96, 128, 144, 192, 256, 288, 384, 512};
 static bool det_size_ok(int M) {
   for (int v : kDetSizes)
     if (v == M) return true;

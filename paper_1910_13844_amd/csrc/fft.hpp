@@ -91,6 +91,8 @@ template <> struct Plan<256> { static constexpr int E = 8;  static constexpr int
 template <> struct Plan<512> { static constexpr int E = 8;  static constexpr int NP = 3; static constexpr int R[5] = {8, 8, 8, 1, 1}; };
 template <> struct Plan<96>  { static constexpr int E = 12; static constexpr int NP = 4; static constexpr int R[5] = {3, 4, 4, 2, 1}; };
 template <> struct Plan<192> { static constexpr int E = 12; static constexpr int NP = 4; static constexpr int R[5] = {3, 4, 4, 4, 1}; };
+template <> struct Plan<144> { static constexpr int E = 36; static constexpr int NP = 4; static constexpr int R[5] = {4, 4, 3, 3, 1}; };
+template <> struct Plan<288> { static constexpr int E = 36; static constexpr int NP = 5; static constexpr int R[5] = {4, 4, 2, 3, 3}; };
 template <> struct Plan<384> { static constexpr int E = 12; static constexpr int NP = 5; static constexpr int R[5] = {3, 4, 4, 4, 2}; };
 
 template <int N>

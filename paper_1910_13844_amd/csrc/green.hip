@@ -214,6 +214,7 @@ static hipError_t fft3(int M, int dir, cplx<double>* d, const cplx<double>* tw, 
     LS_F3(128)
     LS_F3(192)
     LS_F3(256)
+    LS_F3(288)
     LS_F3(384)
     LS_F3(512)
     default: return hipErrorInvalidValue;
@@ -232,8 +233,10 @@ static hipError_t fft2(int M, int dir, cplx<double>* d, int planes, const cplx<d
     LS_F2(64)
     LS_F2(96)
     LS_F2(128)
+    LS_F2(144)
     LS_F2(192)
     LS_F2(256)
+    LS_F2(288)
     LS_F2(384)
     LS_F2(512)
     default: return hipErrorInvalidValue;

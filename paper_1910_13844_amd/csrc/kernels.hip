@@ -804,8 +804,9 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
 template <typename T, int N>
 struct ClassCfg {
   // number of classes; 2 = k_yz3
-  static constexpr int C = sizeof(T) == 4 ? (N <= 96 ? 2 : (N == 128 ? 4 : (N == 192 ? 12 : 16)))
-                                          : (N <= 64 ? 2 : (N == 96 ? 6 : (N == 128 ? 8 : (N == 192 ? 12 : 16))));
+  static constexpr int C = N == 144 ? 18
+                          : sizeof(T) == 4 ? (N <= 96 ? 2 : (N == 128 ? 4 : (N == 192 ? 12 : 16)))
+                                           : (N <= 64 ? 2 : (N == 96 ? 6 : (N == 128 ? 8 : (N == 192 ? 12 : 16))));
   static constexpr int M = 2 * N / C;
   static constexpr int NT = 256;
   static constexpr int PITCH = M + 1;
@@ -1363,6 +1364,7 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
     case 64: return FN<float, 64>(__VA_ARGS__);           \
     case 96: return FN<float, 96>(__VA_ARGS__);           \
     case 128: return FN<float, 128>(__VA_ARGS__);         \
+    case 144: return FN<float, 144>(__VA_ARGS__);         \
     case 192: return FN<float, 192>(__VA_ARGS__);         \
     case 256: return FN<float, 256>(__VA_ARGS__);         \
     default: return hipErrorInvalidValue;                 \
@@ -1375,6 +1377,7 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
     case 64: return FN<double, 64>(__VA_ARGS__);          \
     case 96: return FN<double, 96>(__VA_ARGS__);          \
     case 128: return FN<double, 128>(__VA_ARGS__);        \
+    case 144: return FN<double, 144>(__VA_ARGS__);        \
     case 192: return FN<double, 192>(__VA_ARGS__);        \
     case 256: return FN<double, 256>(__VA_ARGS__);        \
     default: return hipErrorInvalidValue;                 \
@@ -1388,7 +1391,7 @@ static hipError_t ffT_t(const PassArgs& a, hipStream_t s) {
 
 bool fused_supported(int n, bool dbl) {
   (void)dbl;
-  return n == 8 || n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
+  return n == 8 || n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 144 || n == 192 || n == 256;
 }
 
 

@@ -48,7 +48,7 @@ def test_geometry_validation(lib):
     assert lib.ls_kernel_bytes(C.byref(geom(xg=10.0)), C.byref(b)) == -1       # plane outside Omega
     assert lib.ls_kernel_bytes(C.byref(geom(n=48, xg=48.0)), C.byref(b)) == -3             # no kernels for n = 48
     assert lib.ls_kernel_bytes(C.byref(geom(n=512, prec=1, xg=512.0)), C.byref(b)) == -3   # nor for n = 512
-    for n in (192, 256):
+    for n in (144, 192, 256):
         for prec in (0, 1):
             assert lib.ls_kernel_bytes(C.byref(geom(n=n, prec=prec, xg=float(n))), C.byref(b)) == 0
     assert lib.ls_kernel_bytes(None, C.byref(b)) == -1

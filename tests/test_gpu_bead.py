@@ -4,9 +4,8 @@ Lippmann-Schwinger model (GPU) and of the Born model (GPU operator) against the 
 (oracle.mie) on the central x-z plane.
 
 The paper shows the fields as images only (no numbers), so this is a physics check with its own
-bars: the LS error is a few percent (voxelised sphere) and far below the Born error.  Run at
-n = 128 (an 8 lambda0 box): the paper's n = 144 needs transform lengths with a factor 3^2, which
-the plane kernels do not provide.
+bars: the LS error is below a percent or so (voxelised sphere) and far below the Born error.  Run
+at the paper's n = 144 (a 9 lambda0 box, transform lengths 144 and 288) and at n = 128.
 """
 import numpy as np
 import pytest
@@ -21,8 +20,8 @@ from paper_1910_13844_amd import api, workloads  # noqa: E402
 DEV = "cuda:0"
 
 
-def test_bead_ls_vs_born_vs_mie():
-    n = 128
+@pytest.mark.parametrize("n", [144, 128])
+def test_bead_ls_vs_born_vs_mie(n):
     eta_b, eta_s, h_over_lambda = 1.3388, 1.4388, 1.0 / 16.0
     radius = 1.5 / h_over_lambda                          # 3 lambda0 diameter, in voxels
     k = workloads.k_of(h_over_lambda, eta_b)

@@ -1,4 +1,5 @@
-"""GPU parity on grids whose n x n plane does not fit in LDS (n = 192, 256; n = 128 in complex128).
+"""GPU parity on grids whose n x n plane does not fit in LDS (n = 144, 192, 256; n = 128 in
+complex128); n = 144 also exercises the radix-3 transform lengths (144, 288).
 
 There the (y,z) pass runs as two kernels (ky-class fold + z-convolution, then the cropped inverse
 y-DFT over z tiles) and the far field streams z-rows through LDS.  The oracle's Proposition 2
@@ -62,7 +63,8 @@ def cdt(prec):
     return torch.complex128 if prec == "c128" else torch.complex64
 
 
-@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (192, "c64", 4e-6), (192, "c128", 1e-12),
+@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (144, "c64", 4e-6), (144, "c128", 1e-12),
+                                        (192, "c64", 4e-6), (192, "c128", 1e-12),
                                         (256, "c64", 4e-6), (256, "c128", 1e-12)])
 def test_apply_G_big(n, prec, tol):
     v, ref = G_ref(n)
@@ -73,7 +75,7 @@ def test_apply_G_big(n, prec, tol):
     assert e < tol, (n, prec, e)
 
 
-@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (256, "c64", 4e-6)])
+@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (144, "c64", 4e-6), (256, "c64", 4e-6)])
 def test_farfield_big(n, prec, tol):
     u = workloads.random_field(12, (1, n, n, n))
     f = workloads.blob_potential(3, n, dn_max=0.1)
@@ -86,7 +88,7 @@ def test_farfield_big(n, prec, tol):
     assert e < tol
 
 
-@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (256, "c64", 4e-6)])
+@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (144, "c128", 1e-12), (256, "c64", 4e-6)])
 def test_farfield_adjoint_big(n, prec, tol):
     r = workloads.random_field(13, (1, n, n))
     c = ctx(n, prec)
