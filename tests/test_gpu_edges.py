@@ -1,0 +1,74 @@
+"""Edge cases through the C ABI: batches larger than the workspace (processed in groups), a single
+illumination, argument errors, and bitwise determinism of repeated calls.
+
+A group's results must not depend on how the batch is split: the slots never interact and every
+reduction runs in a fixed order, so solutions, detector fields and gradients computed with a
+workspace for two illuminations equal those computed with room for all of them, bit for bit.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1910_13844_amd import _lib, api, workloads  # noqa: E402
+
+K = workloads.k_of()
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def c():
+    return api.Context(32, K, p=4, xg=32.0, prec="c64", device=DEV)
+
+
+def test_forward_split_into_groups_is_bitwise_identical(c):
+    n, Q = 32, 5
+    f = torch.from_numpy(workloads.blob_potential(0, n, dn_max=0.05).astype(np.float32)).to(DEV)
+    dirs = workloads.cone_dirs(Q, 45.0)
+    u_full, i_full = c.ls_forward(f, dirs, tol=1e-6)
+    per2 = c.workspace_bytes(2, _lib.LS_OP_FORWARD)
+    ws_small = torch.empty(per2, dtype=torch.uint8, device=DEV)      # room for 2 of the 5
+    u_grp, i_grp = c.ls_forward(f, dirs, tol=1e-6, ws=ws_small)
+    assert torch.equal(u_full, u_grp)
+    assert [i["iters"] for i in i_full] == [i["iters"] for i in i_grp]
+    y_full = c.ls_farfield(f, u_full)
+    y_grp = c.ls_farfield(f, u_full, ws=torch.empty(c.workspace_bytes(2, _lib.LS_OP_FARFIELD), dtype=torch.uint8,
+                                                    device=DEV))
+    assert torch.equal(y_full, y_grp)
+    # and the same again: repeated calls are deterministic
+    u_again, _ = c.ls_forward(f, dirs, tol=1e-6)
+    assert torch.equal(u_full, u_again)
+
+
+def test_gradient_split_into_groups_is_bitwise_identical(c):
+    n, Q = 32, 4
+    f0, ft = workloads.perturbed_potential(n)
+    f0t = torch.from_numpy(f0.astype(np.float32)).to(DEV)
+    dirs = workloads.cone_dirs(Q, 40.0)
+    u, _ = c.ls_forward(torch.from_numpy(ft.astype(np.float32)).to(DEV), dirs, tol=1e-6)
+    y = c.ls_farfield(torch.from_numpy(ft.astype(np.float32)).to(DEV), u)
+    l1, g1, _ = c.ls_grad(f0t, dirs, y, tol=1e-6)
+    ws_small = torch.empty(c.workspace_bytes(1, _lib.LS_OP_GRAD), dtype=torch.uint8, device=DEV)
+    l2, g2, _ = c.ls_grad(f0t, dirs, y, tol=1e-6, ws=ws_small)
+    # the gradient accumulates group by group in FP64 and is rounded once: same bits either way
+    assert torch.equal(g1, g2) and l1 == l2
+
+
+def test_single_illumination_and_errors(c):
+    n = 32
+    f = torch.zeros((n, n, n), dtype=torch.float32, device=DEV)
+    u, info = c.ls_forward(f, [[0.0, 0.0, 1.0]], tol=1e-6)
+    assert u.shape == (1, n, n, n) and info[0]["status"] == 0 and info[0]["iters"] <= 1
+    uin = np.exp(1j * K * (np.arange(n) - n // 2 + 1))[:, None, None] * np.ones((1, n, n))   # f = 0: u = u_in
+    assert np.abs(u[0].cpu().numpy() - uin).max() < 1e-5
+    with pytest.raises(_lib.LSError):
+        c.ls_forward(f, np.zeros((0, 3)), tol=1e-6)                           # Q = 0
+    with pytest.raises(_lib.LSError):
+        c.ls_forward(f, [[0.0, 0.0, 1.0]], tol=-1.0)                          # bad tolerance
+    tiny = torch.empty(16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(_lib.LSError):
+        c.ls_forward(f, [[0.0, 0.0, 1.0]], tol=1e-6, ws=tiny)                 # workspace too small
+    with pytest.raises(ValueError):
+        c.ls_forward(torch.zeros((n, n, n - 1), dtype=torch.float32, device=DEV), [[0, 0, 1]])
