@@ -197,7 +197,7 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64 fields, f64 reductions" if W.precision == "c64" else "c128",
-        "data": "synthetic (seeded 20-blob phantom, plane waves on a 45-degree cone)",
+        "data": data_description(W),
         "config": {"workload": W.name, "n": n, "padded_fft": 2 * n, "illuminations": Q, "tol": W.tol,
                    "detector": f"{n}x{n}", "p": W.p, "green_init_ms": round(t_init * 1e3, 1)},
         "solve": {"solves_per_step": len(last), "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
@@ -234,6 +234,13 @@ def measured_traffic(workload, kernel):
         return float(vals[f"traffic_bytes_per_launch {kernel}"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def data_description(W):
+    if W.phantom == "sphere":
+        return "synthetic (homogeneous sphere, radius 10 voxels, index 1.36; one plane wave along +z)"
+    return (f"synthetic (seeded 20-blob phantom, dn <= {W.dn_max}; {W.Q} plane waves on a "
+            f"{W.theta_deg:g}-degree cone)")
 
 
 def cpu_baseline(W, f_np, dirs, u, mv_per_solve, per_step=1, grad_mode=False):

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from oracle import grad as ograd  # noqa: E402
-from oracle import incident, kernel, ops, solver  # noqa: E402
+from oracle import incident, kernel, mie, ops, solver  # noqa: E402
 from paper_1910_13844_amd import api, workloads  # noqa: E402
 
 K = workloads.k_of()
@@ -53,6 +53,17 @@ def test_config_A_sphere_c128_matches_oracle_iterates():
     assert info[0]["iters"] == io.iters
     assert rel(u[0].cpu().numpy(), uo) < 1e-10
     assert abs(info[0]["relres_true"] - io.relres_true) <= 1e-6 * io.relres_true
+    # physics: the sphere's total field against the Mie series over the whole box (a voxelised
+    # sphere of radius 10 at 8 points per wavelength: a few 1e-3; the Born field is ~7x worse)
+    cc = workloads.voxel_coords(32)
+    Z, Y, X = np.meshgrid(cc, cc, cc, indexing="ij")
+    ref = mie.total_field_points(K, 1.36 / workloads.ETA_B, 10.0,
+                                 np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)).reshape(32, 32, 32)
+    b = incident.plane_wave(32, K, [0, 0, 1])
+    born = 2 * b - c.ls_apply_A(torch.from_numpy(f).to(DEV), torch.from_numpy(b[None]).to(DEV))[0].cpu().numpy()
+    e_ls, e_born = rel(u[0].cpu().numpy(), ref), rel(born, ref)
+    print(f"[A] {info[0]['iters']} iterations; total field vs Mie: LS {e_ls:.2e}, Born {e_born:.2e}", flush=True)
+    assert e_ls < 1e-2 and e_ls < 0.3 * e_born
 
 
 def test_cone_batch_c128():
