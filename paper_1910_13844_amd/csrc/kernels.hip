@@ -323,17 +323,18 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   constexpr int CM = CL == 1 ? N : 2 * N / CL;
   constexpr int TPP = CM / TY;   // y tiles per period
   constexpr int FA = NYT / TPP;  // periods per row: tiles reading the same class rows
-  const int per = a.nz * NYT;
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   // consecutive blocks on one XCD are the FA tiles of one (slot, z) that read the same class
-  // values, so all but the first find them in L2
+  // values, so all but the first find them in L2.  The order is z-major over all slots, so each
+  // XCD holds a share of every slot and a launch with few active slots still uses all of them.
   const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
-  const int slot = lin / per;
-  const int blk = lin - slot * per;
+  const int zs = lin / NYT;
+  const int tr = lin - zs * NYT;
+  const int z = zs / a.nslots;
+  const int slot = zs - z * a.nslots;
   if (!slot_active(a, slot)) return;
-  const int z = blk / NYT;
-  const int tr = blk - z * NYT;
+  const int blk = z * NYT + tr;
   const int y0 = ((tr / FA) + (tr % FA) * TPP) * TY;
   const SlotDesc& d = a.desc[slot];
   for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
