@@ -326,13 +326,17 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   // consecutive blocks on one XCD are the FA tiles of one (slot, z) that read the same class
-  // values, so all but the first find them in L2.  The order is z-major over all slots, so each
-  // XCD holds a share of every slot and a launch with few active slots still uses all of them.
+  // values, so all but the first find them in L2.  Each XCD takes one eighth of the z range for
+  // every slot (runs of consecutive z per slot), so a launch with few active slots still uses
+  // all XCDs.
   const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
   const int zs = lin / NYT;
   const int tr = lin - zs * NYT;
-  const int z = zs / a.nslots;
-  const int slot = zs - z * a.nslots;
+  const int ZB = (a.nz % 8 == 0) ? a.nz / 8 : 1;
+  const int zb = zs / (a.nslots * ZB);
+  const int rem = zs - zb * a.nslots * ZB;
+  const int slot = rem / ZB;
+  const int z = zb * ZB + (rem - slot * ZB);
   if (!slot_active(a, slot)) return;
   const int blk = z * NYT + tr;
   const int y0 = ((tr / FA) + (tr % FA) * TPP) * TY;
