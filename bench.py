@@ -6,7 +6,7 @@ phantom seed 0, complex64 fields with FP64 reductions) + ls_farfield (128 x 128 
 illumination).  Inputs are resident in HBM before the timed region; the one-time Green-kernel
 build is timed separately.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -32,7 +32,7 @@ def pct(a, q):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="B")
     ap.add_argument("--prof-reps", type=int, default=5)
@@ -198,7 +198,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "c64 fields, f64 reductions" if W.precision == "c64" else "c128",
         "data": data_description(W),
-        "config": {"workload": W.name, "n": n, "padded_fft": 2 * n, "illuminations": Q, "tol": W.tol,
+        "config": {"workload": W.name, "n": n, "padded_fft": 2 * n, "illuminations": Q, "group_size": Q, "tol": W.tol,
                    "detector": f"{n}x{n}", "p": W.p, "green_init_ms": round(t_init * 1e3, 1)},
         "solve": {"solves_per_step": len(last), "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
                   "matvecs_mean": float(np.mean(mvs)), "relres_true_max": float(max(relres))},

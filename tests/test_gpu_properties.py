@@ -1,0 +1,105 @@
+"""Properties of the discrete model that hold at any size, checked on the GPU at the full sizes
+and in the launch configuration the benchmark times (128^3 x 60 illuminations; 256^3).
+
+- Symmetry of G (the kernel gm[k - k'] is even, so G^T = G): a . (G b) = b . (G a) without
+  conjugation, for random volumes (Proposition 2; the discrete operator is a convolution).
+- Reciprocity of the scattering problem (a consequence of that symmetry): for plane waves a, b
+  and the solutions u_a, u_b of (I - G diag f) u = u_in, sum b . f . u_a = sum a . f . u_b.
+- Born limit: for a potential eps f the solution differs from the Born field u_in + G(eps f u_in)
+  by O(eps^2), so halving eps divides the difference by ~4.  The complex128 distances are also
+  compared with the oracle's at 128^3 (stored by tests/golden/make_fullsize.py): 1e-9 relative.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import incident  # noqa: E402
+from paper_1910_13844_amd import api, workloads  # noqa: E402
+
+DEV = "cuda:0"
+_ctx = {}
+
+
+def ctx(n, prec):
+    if (n, prec) not in _ctx:
+        W = workloads.WORKLOADS["B"]
+        print(f"[ctx] n={n} prec={prec}", flush=True)
+        _ctx[(n, prec)] = api.Context(n, W.k, p=4, xg=float(n), prec=prec, device=DEV)
+    return _ctx[(n, prec)]
+
+
+def bdot(a, b):
+    """Bilinear (unconjugated) sum over the last three axes, accumulated in complex128."""
+    return (a.to(torch.complex128) * b.to(torch.complex128)).sum(dim=(-3, -2, -1))
+
+
+@pytest.mark.parametrize("n,prec,tol", [(128, "c64", 2e-6), (128, "c128", 1e-13), (256, "c64", 2e-6)])
+def test_G_is_symmetric(n, prec, tol):
+    c = ctx(n, prec)
+    cd = torch.complex64 if prec == "c64" else torch.complex128
+    g = torch.Generator(device=DEV)
+    g.manual_seed(7)
+    v = torch.randn((2, n, n, n), dtype=cd, device=DEV, generator=g)
+    Gv = c.ls_apply_G(v)
+    lhs, rhs = bdot(v[0], Gv[1]).item(), bdot(v[1], Gv[0]).item()
+    scale = float(torch.linalg.vector_norm(v[0].to(torch.complex128)) * torch.linalg.vector_norm(Gv[1].to(torch.complex128)))
+    print(f"[sym] n={n} {prec}: |a.Gb - b.Ga| / (|a||Gb|) = {abs(lhs - rhs) / scale:.2e}", flush=True)
+    assert abs(lhs - rhs) <= tol * scale
+
+
+def test_reciprocity_at_benchmark_size():
+    # the 60-illumination batch of the benchmark, solved at its tolerance in complex64
+    W = workloads.WORKLOADS["B"]
+    n = W.n
+    c = ctx(n, "c64")
+    f = W.potential()
+    dirs = W.dirs()
+    ft = torch.from_numpy(f.astype(np.float32)).to(DEV)
+    u, info = c.ls_forward(ft, dirs, tol=W.tol)
+    assert all(i["status"] == 0 for i in info)
+    fu = ft.to(torch.float64) * u.to(torch.complex128)
+    # for distant directions the sums are high-frequency Fourier coefficients of f u / u_in and
+    # much smaller than the norms, so the difference is measured against |u_in| |f u| (the
+    # Cauchy-Schwarz bound of either sum)
+    worst = 0.0
+    for qa, qb in ((0, 1), (0, 30), (7, 44), (15, 59)):
+        ua = torch.from_numpy(incident.plane_wave(n, W.k, dirs[qa])).to(DEV)
+        ub = torch.from_numpy(incident.plane_wave(n, W.k, dirs[qb])).to(DEV)
+        lhs = (ub * fu[qa]).sum().item()
+        rhs = (ua * fu[qb]).sum().item()
+        scale = float(torch.linalg.vector_norm(ub) * torch.linalg.vector_norm(fu[qa]))
+        print(f"[reciprocity] q = {qa}, {qb}: sums {abs(lhs):.4e}, {abs(rhs):.4e}; difference / scale "
+              f"{abs(lhs - rhs) / scale:.2e}", flush=True)
+        worst = max(worst, abs(lhs - rhs) / scale)
+    assert worst < 1e-5
+
+
+def test_born_limit_is_second_order():
+    # also a full-size parity pin: the distances equal the oracle's (tests/golden/oracle_fullsize.json,
+    # written by tests/golden/make_fullsize.py from the oracle alone)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_fullsize.json")))["born128"]
+    n = gold["n"]
+    c = ctx(n, "c128")
+    f1 = torch.from_numpy(workloads.blob_potential(gold["seed"], n, dn_max=gold["dn_max"])).to(DEV)
+    d = workloads.cone_dirs(1, 45.0)
+    assert np.allclose(d[0], gold["dir"]) and abs(workloads.WORKLOADS["B"].k - gold["k"]) < 1e-15
+    uin = torch.from_numpy(incident.plane_wave(n, gold["k"], d[0])).to(DEV)[None].contiguous()
+    errs, iters = [], []
+    for eps in gold["eps"]:
+        f = (eps * f1).contiguous()
+        u, info = c.ls_forward(f, d, tol=gold["tol"], maxit=1000)
+        assert info[0]["status"] == 0
+        born = 2 * uin - c.ls_apply_A(f, uin)          # u_in + G (f u_in)
+        errs.append(float(torch.linalg.vector_norm(u - born)))
+        iters.append(info[0]["iters"])
+    print(f"[born] 128^3: |u - u_Born| at eps = 1/2, 1/4, 1/8: {errs} ({iters} iterations); oracle "
+          f"{gold['err']} ({gold['iters']})", flush=True)
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+    for e, g, i, gi in zip(errs, gold["err"], iters, gold["iters"]):
+        assert abs(e - g) <= 1e-9 * g and abs(i - gi) <= 1

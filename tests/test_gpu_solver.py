@@ -64,6 +64,22 @@ def test_config_A_sphere_c128_matches_oracle_iterates():
     e_ls, e_born = rel(u[0].cpu().numpy(), ref), rel(born, ref)
     print(f"[A] {info[0]['iters']} iterations; total field vs Mie: LS {e_ls:.2e}, Born {e_born:.2e}", flush=True)
     assert e_ls < 1e-2 and e_ls < 0.3 * e_born
+    # and at the detector plane x3 = x_Gamma = 32: scattered field y = G~(f u) against Mie's
+    ft = torch.from_numpy(f).to(DEV)
+    y = c.ls_farfield(ft, u)[0].cpu().numpy()
+    yb = c.ls_farfield(ft, torch.from_numpy(b[None]).to(DEV))[0].cpu().numpy()
+    Yd, Xd = np.meshgrid(cc, cc, indexing="ij")
+    pts = np.stack([Xd.ravel(), Yd.ravel(), np.full(Xd.size, 32.0)], 1)
+    ref_y = (mie.total_field_points(K, 1.36 / workloads.ETA_B, 10.0, pts) - np.exp(1j * K * 32.0)).reshape(32, 32)
+    ey_ls, ey_born = rel(y, ref_y), rel(yb, ref_y)
+    print(f"[A] detector field vs Mie: LS {ey_ls:.2e}, Born {ey_born:.2e}", flush=True)
+    assert ey_ls < 1e-2 and ey_ls < 0.1 * ey_born
+    # the complex64 run of the same problem: within 1e-4 of the FP64 oracle
+    c64 = ctx(32, "c64")
+    u32, i32 = c64.ls_forward(torch.from_numpy(f.astype(np.float32)).to(DEV), [[0, 0, 1]], tol=1e-6)
+    e32 = rel(u32[0].cpu().numpy(), uo)
+    print(f"[A] complex64 (tol 1e-6): {i32[0]['iters']} iterations, vs oracle {e32:.2e}", flush=True)
+    assert i32[0]["status"] == 0 and e32 < 1e-4
 
 
 def test_cone_batch_c128():
