@@ -183,6 +183,8 @@ def main() -> int:
         metric = f"data-term gradients/sec at {n}^3x{Q} views ({W.precision}, tol {W.tol:g}); p50/p99 ms"
     else:
         metric = f"LS solves/sec at {n}^3x{Q} illum ({W.precision}, tol {W.tol:g}); p50/p99 ms"
+    solve_ms = [i["time_ms"] for step_info in infos for i in step_info]
+    assert min(solve_ms) > 0, "every solve reports its device completion time"
     out = {
         "metric": metric,
         "value": round(value, 3),
@@ -191,8 +193,12 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(1e3 * total / args.steps, 2),
-        "p50_ms": round(pct(times, 50), 2),
-        "p99_ms": round(pct(times, 99), 2),
+        # per-solve completion time over all timed steps: device clock from the batch's first pass
+        # to the step at which that illumination's solve reached its final state
+        "p50_ms": round(pct(solve_ms, 50), 2),
+        "p99_ms": round(pct(solve_ms, 99), 2),
+        "step_p50_ms": round(pct(times, 50), 2),
+        "step_p99_ms": round(pct(times, 99), 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

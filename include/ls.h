@@ -64,6 +64,8 @@ typedef struct {
   int32_t restarts;
   double relres_rec;   /* last recursive relative residual */
   double relres_true;  /* ||b - A x|| / ||b|| recomputed from x (FP64 accumulation) */
+  double time_ms;      /* device-clock time from the illumination's first pass (its initial
+                          residual) to its final state; -1 if it has not reached one */
 } ls_solve_info;
 
 typedef struct ls_ctx ls_ctx;     /* immutable after ls_green_init; host-side object */

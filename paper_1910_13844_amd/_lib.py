@@ -38,7 +38,7 @@ class SolveOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("matvecs", C.c_int32), ("restarts", C.c_int32),
-                ("relres_rec", C.c_double), ("relres_true", C.c_double)]
+                ("relres_rec", C.c_double), ("relres_true", C.c_double), ("time_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

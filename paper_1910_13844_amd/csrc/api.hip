@@ -25,6 +25,7 @@ struct ls_ctx {
   void* tw;
   void* kvol;
   void* kff;
+  double clk_khz;  // rate of the device steady clock (ticks per ms)
 };
 
 namespace {
@@ -207,7 +208,7 @@ int solve_all(const Run& r, std::vector<SlotState>& h) {
   return LS_ERR_HIP;
 }
 
-void to_info(const SlotState& s, ls_solve_info* o) {
+void to_info(const SlotState& s, double clk_khz, ls_solve_info* o) {
   int st = 1;
   switch (s.status) {
     case ST_OK: st = 0; break;
@@ -222,6 +223,7 @@ void to_info(const SlotState& s, ls_solve_info* o) {
   o->restarts = s.restarts;
   o->relres_rec = s.relres;
   o->relres_true = s.relres_true;
+  o->time_ms = (s.t_done > s.t_start && s.t_start > 0 && clk_khz > 0) ? (double)(s.t_done - s.t_start) / clk_khz : -1.0;
 }
 
 SlotState init_state(const ls_solve_opts* o, int status) {
@@ -393,6 +395,9 @@ int ls_green_init(const ls_geom* g, void* kbuf, size_t kbuf_bytes, void* ws, siz
   if (kbuf_bytes < KL.total || ws_bytes < init_ws_bytes(g->n)) return LS_ERR_WORKSPACE;
   hipError_t e = green_build(g->n, g->p, g->kbh, g->xg, dbl, kbuf, ws, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "green_build");
+  int dev = 0, clk = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, dev) != hipSuccess) clk = 0;
   ls_ctx* c = new (std::nothrow) ls_ctx;
   if (!c) return LS_ERR_ARG;
   c->g = *g;
@@ -404,6 +409,7 @@ int ls_green_init(const ls_geom* g, void* kbuf, size_t kbuf_bytes, void* ws, siz
   c->tw = c->kbuf + KL.off_tw;
   c->kvol = c->kbuf + KL.off_vol;
   c->kff = c->kbuf + KL.off_ff;
+  c->clk_khz = (double)clk;
   *out = c;
   return LS_OK;
 }
@@ -610,7 +616,7 @@ static int forward_common(const ls_ctx* c, const void* f, int32_t Q, const doubl
     if (rc) return rc;
     if ((rc = solve_all(r, h))) return rc;
     if (info)
-      for (int i = 0; i < nq; ++i) to_info(h[i], info + q0 + i);
+      for (int i = 0; i < nq; ++i) to_info(h[i], c->clk_khz, info + q0 + i);
   }
   return LS_OK;
 }
@@ -734,7 +740,7 @@ static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* 
     if (full) {
       if ((rc = solve_all(rf, h))) return rc;
       if (info)
-        for (int i = 0; i < nq; ++i) to_info(h[i], info + q0 + i);
+        for (int i = 0; i < nq; ++i) to_info(h[i], c->clk_khz, info + q0 + i);
       // y = G~(f . u) into the detector buffer, then r = y - y_meas in place with FP64 norms
       if ((rc = farfield_run(rf, V_X, V_T, V_AUX, M_ALL))) return rc;
       HIPCHK(launch_residual(c->dbl, c->n, det, (const char*)y_meas + (size_t)q0 * M * c->csz, nq, det,
@@ -750,7 +756,7 @@ static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* 
     if ((rc = solve_all(ra, h))) return rc;
     if (info) {
       ls_solve_info* base = full ? info + Q : info;
-      for (int i = 0; i < nq; ++i) to_info(h[i], base + q0 + i);
+      for (int i = 0; i < nq; ++i) to_info(h[i], c->clk_khz, base + q0 + i);
     }
     HIPCHK(launch_grad_accum(c->dbl, c->n, (const SlotDesc*)(w + L.off_desc[2]), full ? d_stats : nullptr, nq, V_X,
                              V_R, d_grad, q0 > 0 ? 1 : 0, s));
@@ -1055,7 +1061,7 @@ int ls_batch_poll(const ls_batch* b, int32_t* state, ls_solve_info* info) {
   for (int i = 0; i < b->nslots; ++i) {
     const SlotState& s = b->hs[i];
     if (state) state[i] = s.status == ST_IDLE ? 0 : (busy(s) ? 1 : 2);
-    if (info) to_info(s, info + i);
+    if (info) to_info(s, b->c->clk_khz, info + i);
   }
   return LS_OK;
 }

@@ -207,6 +207,10 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
   const int y0 = (blk - z * NYT) * TY;
   const SlotDesc& d = a.desc[slot];
   const SlotState& st = a.st[slot];
+  if constexpr (MODE == PRO_F_B) {
+    // the initial-residual pass is a slot's first work: its start time on the device clock
+    if (blk == 0 && tid == 0) a.st[slot].t_start = (uint64_t)wall_clock64();
+  }
   for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
 
   const size_t row0 = ((size_t)z * N + y0) * N;
@@ -1126,6 +1130,13 @@ __device__ __forceinline__ void fresh_restart(SlotState& st) {
   st.rho_prev[1] = st.alpha[1] = st.omega[1] = 0.0;
 }
 
+__device__ __forceinline__ bool final_state(int s) {
+  return s == ST_OK || s == ST_MAXIT || s == ST_BREAK || s == ST_NONFIN;
+}
+
+template <int KIND>
+__device__ __forceinline__ void scalar_update(SlotState& st, const double (&v)[6], double eps);
+
 template <int KIND>
 __global__ __launch_bounds__(256) void k_scalar(PassArgs a, double eps) {
   __shared__ double red[6 * 4];
@@ -1141,6 +1152,14 @@ __global__ __launch_bounds__(256) void k_scalar(PassArgs a, double eps) {
   block_sum<6>(v, red);
   if (tid != 0) return;
   SlotState& st = a.st[slot];
+  const int s0 = st.status;
+  scalar_update<KIND>(st, v, eps);
+  if (final_state(st.status) && !final_state(s0)) st.t_done = (uint64_t)wall_clock64();
+}
+
+// One step of the per-slot BiCGSTAB scalar recurrence from the block-summed partials v.
+template <int KIND>
+__device__ __forceinline__ void scalar_update(SlotState& st, const double (&v)[6], double eps) {
   const cplx<double> p0 = {v[0], v[1]}, p1 = {v[2], v[3]}, p2 = {v[4], v[5]};
   if (KIND == SC_INIT) {
     st.matvecs += 1;

@@ -1,10 +1,13 @@
 """Edge cases through the C ABI: batches larger than the workspace (processed in groups), a single
-illumination, argument errors, and bitwise determinism of repeated calls.
+illumination, argument errors, bitwise determinism of repeated calls, and the device-recorded
+completion time of each solve.
 
 A group's results must not depend on how the batch is split: the slots never interact and every
 reduction runs in a fixed order, so solutions, detector fields and gradients computed with a
 workspace for two illuminations equal those computed with room for all of them, bit for bit.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -72,3 +75,29 @@ def test_single_illumination_and_errors(c):
         c.ls_forward(f, [[0.0, 0.0, 1.0]], tol=1e-6, ws=tiny)                 # workspace too small
     with pytest.raises(ValueError):
         c.ls_forward(torch.zeros((n, n, n - 1), dtype=torch.float32, device=DEV), [[0, 0, 1]])
+
+
+def test_device_completion_times(c):
+    n, Q = 32, 6
+    f = torch.from_numpy(workloads.blob_potential(1, n, dn_max=0.1).astype(np.float32)).to(DEV)
+    dirs = workloads.cone_dirs(Q, 45.0)
+    c.ls_forward(f, dirs, tol=1e-6)                     # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = c.ls_forward(f, dirs, tol=1e-6)
+    wall = (time.perf_counter() - t0) * 1e3
+    ts = [i["time_ms"] for i in info]
+    its = [i["iters"] for i in info]
+    print(f"[times] iterations {its}, device ms {[round(t, 3) for t in ts]}, call {wall:.3f} ms", flush=True)
+    assert all(0 < t <= wall for t in ts)
+    # the slots advance in lockstep: one that needed more iterations finished later
+    for a in range(Q):
+        for b in range(Q):
+            if its[b] > its[a]:
+                assert ts[b] > ts[a]
+    # gradient calls report both solves of every view
+    f0, ft = workloads.perturbed_potential(n)
+    y = c.ls_farfield(torch.from_numpy(ft.astype(np.float32)).to(DEV),
+                      c.ls_forward(torch.from_numpy(ft.astype(np.float32)).to(DEV), dirs, tol=1e-6)[0])
+    _, _, ginfo = c.ls_grad(torch.from_numpy(f0.astype(np.float32)).to(DEV), dirs, y, tol=1e-6)
+    assert len(ginfo) == 2 * Q and all(i["time_ms"] > 0 for i in ginfo)
