@@ -101,3 +101,34 @@ def test_device_completion_times(c):
                       c.ls_forward(torch.from_numpy(ft.astype(np.float32)).to(DEV), dirs, tol=1e-6)[0])
     _, _, ginfo = c.ls_grad(torch.from_numpy(f0.astype(np.float32)).to(DEV), dirs, y, tol=1e-6)
     assert len(ginfo) == 2 * Q and all(i["time_ms"] > 0 for i in ginfo)
+
+
+def test_one_context_two_streams_two_threads(c):
+    # the context is immutable after ls_green_init: two host threads may drive it on two streams
+    # (each with its own workspace) at once, with the same results as one after the other
+    import threading
+    n, Q = 32, 4
+    dirs = workloads.cone_dirs(Q, 45.0)
+    fs = [torch.from_numpy(workloads.blob_potential(s, n, dn_max=0.05).astype(np.float32)).to(DEV) for s in (2, 3)]
+    refs = [c.ls_forward(f, dirs, tol=1e-6)[0] for f in fs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    wss = [torch.empty(c.workspace_bytes(Q, _lib.LS_OP_FORWARD), dtype=torch.uint8, device=DEV) for _ in fs]
+    outs = [torch.empty_like(r) for r in refs]
+    torch.cuda.synchronize()
+    errors = []
+
+    def run(i):
+        try:
+            for _ in range(3):
+                c.ls_forward(fs[i], dirs, tol=1e-6, u=outs[i], ws=wss[i], stream=streams[i])
+        except Exception as e:  # reported after join
+            errors.append(e)
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    torch.cuda.synchronize()
+    assert not errors and not any(t.is_alive() for t in th)
+    assert torch.equal(outs[0], refs[0]) and torch.equal(outs[1], refs[1])
