@@ -27,9 +27,10 @@ from .api import Context
 
 def reconstruct(ctx: Context, dirs, y_meas: torch.Tensor, f0: torch.Tensor, tau: float, gamma0: float,
                 subsets: Sequence[Sequence[int]], tv_iters: int, tol: float = 1e-5, nonneg: bool = True,
-                history: Optional[List[dict]] = None) -> torch.Tensor:
+                history: Optional[List[dict]] = None, f_ref: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Algorithm 1 for len(subsets) iterations.  dirs [Q, 3] (host), y_meas [Q, n, n] (device),
-    f0 [n]^3 (device, the context's real type).  Returns f^K."""
+    f0 [n]^3 (device, the context's real type).  Returns f^K.  With `history`, one record per
+    iteration; with `f_ref` as well, each record holds ||f^k - f_ref|| / ||f_ref||."""
     dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
     f_prev = f0.clone()
     v = f0.clone()
@@ -48,9 +49,11 @@ def reconstruct(ctx: Context, dirs, y_meas: torch.Tensor, f0: torch.Tensor, tau:
         a = a_next
         if history is not None:
             torch.cuda.synchronize()
-            history.append({"k": k, "loss_at_v": loss, "gamma": gamma, "views": sub,
-                            "seconds": time.perf_counter() - t0,
-                            "iters": [i["iters"] for i in info]})
+            rec = {"k": k, "loss_at_v": loss, "gamma": gamma, "views": sub, "seconds": time.perf_counter() - t0,
+                   "iters": [i["iters"] for i in info]}
+            if f_ref is not None:
+                rec["rel_err"] = float((f_prev - f_ref).norm() / f_ref.norm())
+            history.append(rec)
     return f_prev
 
 
@@ -111,12 +114,18 @@ def main(argv=None) -> int:
     f = reconstruct(ctx, dirs, y, f_start, args.tau, gamma0, subs, args.tv_iters, history=hist)
     torch.cuda.synchronize()
     total = time.perf_counter() - t
+    # a second, untimed run that records the error to the truth after every iteration
+    hist_err: List[dict] = []
+    reconstruct(ctx, dirs, y, f_start, args.tau, gamma0, subs, args.tv_iters, history=hist_err, f_ref=ft)
+    marks = sorted({k for k in (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, 2000) if k <= args.iters} | {args.iters})
     err = float((f - ft).norm() / ft.norm())
     print(json.dumps({"n": n, "views": Q, "iters": args.iters, "subset": args.subset, "lipschitz": L_full,
                       "gamma0": gamma0, "tau": args.tau, "tv_iters": args.tv_iters, "seconds": total,
                       "seconds_per_iter": total / args.iters, "rel_err_to_truth": err,
-                      "loss_at_v": [h["loss_at_v"] for h in hist],
-                      "solver_iters_mean": [float(np.mean(h["iters"])) for h in hist]}), flush=True)
+                      "rel_err_at": {k: hist_err[k - 1]["rel_err"] for k in marks},
+                      "loss_at_v_at": {k: hist[k - 1]["loss_at_v"] for k in marks},
+                      "solver_iters_mean_at": {k: float(np.mean(hist[k - 1]["iters"])) for k in marks}}),
+          flush=True)
     return 0
 
 
