@@ -160,11 +160,15 @@ int scalar(const Run& r, int kind, uint32_t mask) {
 
 // Enqueue: initial residuals of admitted slots, then `iters` BiCGSTAB iterations, each followed
 // by the true-residual check of slots whose recursion finished.  Slots not in the state a kernel
-// acts on return immediately, so this needs no host round trip.
-int enqueue_steps(const Run& r, int iters) {
+// acts on return immediately, so this needs no host round trip.  Only the host admits slots, so
+// it knows whether any is waiting for its initial residual (`init`); if none is, those launches
+// are skipped.
+int enqueue_steps(const Run& r, int iters, bool init) {
   int rc;
-  if ((rc = matvec(r, PRO_F_B, 0, EPI_R0, 0, 0, M_INIT))) return rc;
-  if ((rc = scalar(r, SC_INIT, M_INIT))) return rc;
+  if (init) {
+    if ((rc = matvec(r, PRO_F_B, 0, EPI_R0, 0, 0, M_INIT))) return rc;
+    if ((rc = scalar(r, SC_INIT, M_INIT))) return rc;
+  }
   for (int it = 0; it < iters; ++it) {
     if ((rc = matvec(r, PRO_P, 0, EPI_AXV, 0, 0, M_RUN))) return rc;
     if ((rc = scalar(r, SC_ALPHA, M_RUN))) return rc;
@@ -193,11 +197,17 @@ bool busy(const SlotState& s) {
   return s.status == ST_RUN || s.status == ST_HALF || s.status == ST_CHECK || s.status == ST_INIT;
 }
 
+bool any_init(const std::vector<SlotState>& h) {
+  for (const auto& s : h)
+    if (s.status == ST_INIT) return true;
+  return false;
+}
+
 int solve_all(const Run& r, std::vector<SlotState>& h) {
   int rc;
   int chunk = 2;
   for (int guard = 0; guard < 100000; ++guard) {
-    if ((rc = enqueue_steps(r, chunk))) return rc;
+    if ((rc = enqueue_steps(r, chunk, guard == 0 || any_init(h)))) return rc;
     if ((rc = pull_states(r, h))) return rc;
     bool any = false;
     for (const auto& s : h) any = any || busy(s);
@@ -1051,7 +1061,7 @@ int ls_batch_admit(ls_batch* b, int32_t slot, const void* f, const double* dir, 
 int ls_batch_step(ls_batch* b, int32_t iters, void* stream) {
   if (!b || iters < 0) return LS_ERR_ARG;
   Run r = make_run(b->c, b->ws, b->L, b->nslots, 0, (hipStream_t)stream);
-  int rc = enqueue_steps(r, iters);
+  int rc = enqueue_steps(r, iters, any_init(b->hs));
   if (rc) return rc;
   return pull_states(r, b->hs);
 }
