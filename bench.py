@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK = 78.6   # TFLOP/s: 256 CU x 64 FMA lanes/clk x 2 x 2.4 GHz, non-packed FP32
-FP32_PACKED_PEAK = 157.3  # TFLOP/s with packed (2-wide) FP32 FMA, which this build does not use
+FP32_PACKED_PEAK = 157.3  # TFLOP/s with packed (2-wide) FP32 FMA; the kernels are compiled without packed FP32
 
 
 def pct(a, q):
@@ -41,8 +41,8 @@ def main() -> int:
                     help="also run one device-to-device copy of 1 GiB (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X; multi-GPU sharding is "
-              "described in DESIGN.md and not executed", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single MI355X; sharding the illuminations "
+              "over several GPUs is not implemented", file=sys.stderr)
         return 2
 
     import numpy as np

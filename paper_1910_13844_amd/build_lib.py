@@ -3,7 +3,9 @@
     python -m paper_1910_13844_amd.build_lib [--jobs N]
 
 Sources are compiled in parallel to objects under paper_1910_13844_amd/_build/ and linked into
-paper_1910_13844_amd/libls.so.  Packed FP32 instructions are disabled on purpose.
+paper_1910_13844_amd/libls.so.  Packed FP32 instructions are disabled on purpose (the
+-packed-fp32-ops target feature below): some of their forms have produced silently wrong results
+on gfx950.
 """
 from __future__ import annotations
 
