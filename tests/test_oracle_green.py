@@ -21,8 +21,8 @@ def quad_ghat(s, k, R):
         fi = lambda r: np.sin(k * r) * np.sin(s * r)
         sc = 1.0 / s
     lim = 2000
-    re = integrate.quad(fr, 0, R, limit=lim, epsabs=1e-13, epsrel=1e-13)[0]
-    im = integrate.quad(fi, 0, R, limit=lim, epsabs=1e-13, epsrel=1e-13)[0]
+    re = integrate.quad(fr, 0, R, limit=lim, epsabs=1e-12, epsrel=1e-12)[0]
+    im = integrate.quad(fi, 0, R, limit=lim, epsabs=1e-12, epsrel=1e-12)[0]
     return sc * complex(re, im)
 
 
