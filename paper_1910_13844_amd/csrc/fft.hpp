@@ -152,6 +152,31 @@ __device__ __forceinline__ void fft_group(cplx<T>* base, int stride, int lane, c
 }
 
 // ---------------------------------------------------------------------------------------------
+// 24-point DFT in registers by the prime-factor (Good-Thomas) algorithm, 24 = 3 x 8 with 3 and 8
+// coprime, so no twiddles: input n = (8 n1 + 3 n2) mod 24, 8-point DFTs over n2, 3-point DFTs over
+// n1, output k = (16 k1 + 9 k2) mod 24 (k = k1 mod 3, k = k2 mod 8).  Index maps are
+// compile-time, so the permutations cost nothing.
+template <int DIR, typename T>
+struct SmallDFT<24, DIR, T> {
+  static __device__ __forceinline__ void run(cplx<T>* a) {
+    cplx<T> y[3][8];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+#pragma unroll
+      for (int n2 = 0; n2 < 8; ++n2) y[n1][n2] = a[(8 * n1 + 3 * n2) % 24];
+      SmallDFT<8, DIR, T>::run(y[n1]);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+      cplx<T> t[3] = {y[0][k2], y[1][k2], y[2][k2]};
+      SmallDFT<3, DIR, T>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) a[(16 * k1 + 9 * k2) % 24] = t[k1];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------------------
 // 16-point DFT in registers as 4 x 4 with internal twiddles exp(DIR 2 pi i m / 16).
 template <int DIR, typename T>
 struct SmallDFT<16, DIR, T> {
@@ -200,6 +225,8 @@ template <> struct Split<32>  { static constexpr int L = 4, E = 8; };
 template <> struct Split<64>  { static constexpr int L = 8, E = 8; };
 template <> struct Split<128> { static constexpr int L = 8, E = 16; };
 template <> struct Split<256> { static constexpr int L = 16, E = 16; };
+template <> struct Split<96>  { static constexpr int L = 4, E = 24; };
+template <> struct Split<192> { static constexpr int L = 8, E = 24; };
 
 template <int N>
 __device__ __forceinline__ int tpos(int k1, int m) {

@@ -89,7 +89,8 @@ __device__ __forceinline__ double* part_ptr(const PassArgs& a, int slot, int blk
 // the storage order of bpos() (natural order for the Stockham sizes).
 template <int N>
 struct HasSplit {
-  static constexpr bool value = (N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256);
+  static constexpr bool value = (N == 8 || N == 16 || N == 32 || N == 64 || N == 96 || N == 128 || N == 192 ||
+                                 N == 256);
 };
 
 template <typename T, int N, int DIR, int TWS = 2>
@@ -571,12 +572,47 @@ struct alignas(4 * sizeof(T)) cpair {
   cplx<T> a, b;
 };
 
-template <typename T, int N, int PITCH>
+template <typename T, int N, int PITCH, bool LEAN = (Split<N>::E * sizeof(T) > 64)>
 __device__ __forceinline__ void zconv4(cplx<T>* col, int lane, const cplx<T>* tw, const cplx<T>* twl,
                                        const cplx<T>* kr) {
   constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
   const LS_GLOBAL T* k2p = (const LS_GLOBAL T*)kr;
   cplx<T> e[E], o[E];
+  if constexpr (LEAN) {
+    // register-lean order for long per-lane transforms: each parity's kernel samples are loaded
+    // only once its forward transform is done
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int zz = lane + L * j;
+      e[j] = col[zz * PITCH];
+      o[j] = e[j] * tw[zz];
+    }
+    fft_a2b<T, N, -1, 2>(e, col, PITCH, lane, twl);
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int k2 = 0; k2 < L; ++k2) {
+        const LS_GLOBAL T* q = k2p + 4 * (lane * P + t + E * k2);
+        e[t * L + k2] = e[t * L + k2] * cplx<T>{q[0], q[1]};
+      }
+    fft_b2a<T, N, +1, 2>(e, col, PITCH, lane, twl);
+    fft_a2b<T, N, -1, 2>(o, col, PITCH, lane, twl);
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int k2 = 0; k2 < L; ++k2) {
+        const LS_GLOBAL T* q = k2p + 4 * (lane * P + t + E * k2);
+        o[t * L + k2] = o[t * L + k2] * cplx<T>{q[2], q[3]};
+      }
+    fft_b2a<T, N, +1, 2>(o, col, PITCH, lane, twl);
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int zz = lane + L * j;
+      col[zz * PITCH] = e[j] + mulc(o[j], tw[zz]);
+    }
+    return;
+  }
   cpair<T> kk[E];
 #pragma unroll
   for (int t = 0; t < P; ++t)
@@ -830,6 +866,12 @@ struct ClassCfg {
                                            : (N <= 64 ? 2 : (N == 96 ? 6 : (N == 128 ? 8 : (N == 192 ? 12 : 16))));
   static constexpr int M = 2 * N / C;
   static constexpr int NT = 256;
+  // waves per SIMD the register allocation must leave room for (complex128 at 128: two workgroups
+  // per CU at the price of a few spilled registers)
+  static constexpr int WPE = (sizeof(T) == 8 && N == 128) ? 2 : 1;
+  // z-convolution by the register four-step transform (else the in-LDS Stockham one; complex128
+  // at 96 keeps the latter, which needs fewer registers)
+  static constexpr bool ZFOUR = HasSplit<N>::value && !(sizeof(T) == 8 && N == 96);
   static constexpr int PITCH = M + 1;
   static_assert(C == 2 || (HasSplit<M>::value && N % M == 0 && M % 16 == 0), "class slab shape");
 };
@@ -845,7 +887,7 @@ __device__ __forceinline__ void fill_twl_stride(cplx<T>* twl, const cplx<T>* tw,
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__((ClassCfg<T, N>::NT)) void k_yzc(PassArgs a) {
+__global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k_yzc(PassArgs a) {
   using CC = ClassCfg<T, N>;
   constexpr int C = CC::C, M = CC::M, F = N / M, NT = CC::NT, PITCH = CC::PITCH;
   constexpr int LM = Split<M>::L;
@@ -909,7 +951,7 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT)) void k_yzc(PassArgs a) {
     for (int idx = g; idx < N; idx += G) row_fft<T, M, -1>(slab + spreadL<N, LM>(idx) * PITCH, lane, tw, twlM);
   }
   __syncthreads();
-  if constexpr (HasSplit<N>::value) {
+  if constexpr (CC::ZFOUR) {
     constexpr int L = Split<N>::L;
     constexpr int G = NT / L;
     const int g = tid / L, lane = tid - g * L;

@@ -63,7 +63,8 @@ def cdt(prec):
     return torch.complex128 if prec == "c128" else torch.complex64
 
 
-@pytest.mark.parametrize("n,prec,tol", [(128, "c64", 4e-6), (128, "c128", 1e-12), (144, "c64", 4e-6), (144, "c128", 1e-12),
+@pytest.mark.parametrize("n,prec,tol", [(96, "c64", 4e-6), (96, "c128", 1e-12), (128, "c64", 4e-6), (128, "c128", 1e-12),
+                                        (144, "c64", 4e-6), (144, "c128", 1e-12),
                                         (192, "c64", 4e-6), (192, "c128", 1e-12),
                                         (256, "c64", 4e-6), (256, "c128", 1e-12)])
 def test_apply_G_big(n, prec, tol):
@@ -75,7 +76,8 @@ def test_apply_G_big(n, prec, tol):
     assert e < tol, (n, prec, e)
 
 
-@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (144, "c64", 4e-6), (256, "c64", 4e-6)])
+@pytest.mark.parametrize("n,prec,tol", [(96, "c64", 4e-6), (96, "c128", 1e-12), (128, "c128", 1e-12), (144, "c64", 4e-6),
+                                        (192, "c64", 4e-6), (192, "c128", 1e-12), (256, "c64", 4e-6)])
 def test_farfield_big(n, prec, tol):
     u = workloads.random_field(12, (1, n, n, n))
     f = workloads.blob_potential(3, n, dn_max=0.1)
@@ -88,7 +90,8 @@ def test_farfield_big(n, prec, tol):
     assert e < tol
 
 
-@pytest.mark.parametrize("n,prec,tol", [(128, "c128", 1e-12), (144, "c128", 1e-12), (256, "c64", 4e-6)])
+@pytest.mark.parametrize("n,prec,tol", [(96, "c64", 4e-6), (128, "c128", 1e-12), (144, "c128", 1e-12), (192, "c64", 4e-6),
+                                        (256, "c64", 4e-6)])
 def test_farfield_adjoint_big(n, prec, tol):
     r = workloads.random_field(13, (1, n, n))
     c = ctx(n, prec)
