@@ -862,10 +862,12 @@ template <typename T, int N>
 struct ClassCfg {
   // number of classes; 2 = k_yz3
   static constexpr int C = N == 144 ? 18
-                          : sizeof(T) == 4 ? (N <= 96 ? 2 : (N == 128 ? 4 : (N == 192 ? 12 : 16)))
+                          : sizeof(T) == 4 ? (N <= 96 ? 2 : (N == 128 ? 4 : (N == 192 ? 6 : 8)))
                                            : (N <= 64 ? 2 : (N == 96 ? 6 : (N == 128 ? 8 : (N == 192 ? 12 : 16))));
   static constexpr int M = 2 * N / C;
-  static constexpr int NT = 256;
+  // complex64 from 192 up: one 100-140 KB slab per CU, worked on by 8 waves (fewer classes make
+  // the class sum of the x-inverse cheaper than the lost overlap of two workgroups costs)
+  static constexpr int NT = (sizeof(T) == 4 && N >= 192) ? 512 : 256;
   // waves per SIMD the register allocation must leave room for (complex128 at 128: two workgroups
   // per CU at the price of a few spilled registers)
   static constexpr int WPE = (sizeof(T) == 8 && N == 128) ? 2 : 1;
