@@ -25,7 +25,12 @@ def _stream(stream=None) -> int:
 
 
 class Context:
-    """Green kernels of one geometry, resident on the device (ls_green_init)."""
+    """Green kernels of one geometry, resident on the device (ls_green_init).
+
+    The context itself is immutable and may be used from several threads and streams at once.
+    Calls that are not given a workspace (`ws=None`) share one cached workspace per operation, so
+    concurrent calls (other threads or streams) must each pass a workspace of their own.
+    """
 
     def __init__(self, n: int, kbh: float, p: int = 4, xg: Optional[float] = None, prec: str = "c64",
                  device: str = "cuda:0", stream=None):
