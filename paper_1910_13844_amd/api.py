@@ -94,6 +94,16 @@ class Context:
             raise ValueError(f"f: expected contiguous {self.rdtype} [{self.n}]^3 on {self.device}")
         return f
 
+    def _chk_like(self, t: torch.Tensor, shape, dtype, name: str) -> torch.Tensor:
+        """Device, dtype, contiguity and exact shape of a caller tensor (the library only sees pointers)."""
+        if t.device != self.device or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected contiguous {dtype} {list(shape)} on {self.device}, got "
+                             f"{t.dtype} {list(t.shape)} on {t.device}")
+        return t
+
+    def _chk_det_q(self, y: torch.Tensor, Q: int, name: str) -> torch.Tensor:
+        return self._chk_like(y.contiguous(), (Q, self.n, self.n), self.cdtype, name)
+
     @staticmethod
     def _opts(tol: float, maxit: int, max_restarts: int) -> L.SolveOpts:
         return L.SolveOpts(float(tol), int(maxit), int(max_restarts))
@@ -125,7 +135,7 @@ class Context:
         Q = d.shape[0]
         if u is None:
             u = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device)
-        self._chk_vol(u, "u")
+        self._chk_like(u, (Q, self.n, self.n, self.n), self.cdtype, "u")
         ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
         info = (L.SolveInfo * Q)()
         o = self._opts(tol, maxit, max_restarts)
@@ -142,7 +152,7 @@ class Context:
         Q = uin.numel() // self.N
         if u is None:
             u = torch.empty_like(uin)
-        self._chk_vol(u, "u")
+        self._chk_like(u, tuple(uin.shape), self.cdtype, "u")
         ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
         info = (L.SolveInfo * Q)()
         o = self._opts(tol, maxit, max_restarts)
@@ -160,7 +170,7 @@ class Context:
         kt = np.ascontiguousarray(np.zeros((Q, 2)) if ktilde is None else np.asarray(ktilde, dtype=np.float64)
                                   .reshape(Q, 2))
         u = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device) if out is None else out
-        self._chk_vol(u, "out")
+        self._chk_like(u, (Q, self.n, self.n, self.n), self.cdtype, "out")
         ws = self.workspace(Q, L.LS_OP_INCIDENT) if ws is None else ws
         L.check(self.lib.ls_incident_field(self.h, _ptr(y_in), kt.ctypes.data_as(C.POINTER(C.c_double)), Q,
                                            int(bool(tilt)), _ptr(u), _ptr(ws), ws.numel(), _stream(stream)),
@@ -180,8 +190,8 @@ class Context:
 
     def ls_farfield_adj(self, r: torch.Tensor, conj: bool = False, stream=None) -> torch.Tensor:
         r = r.contiguous()
-        if r.dtype != self.cdtype or r.shape[-2:] != (self.n, self.n):
-            raise ValueError("r: expected [Q, n, n] in the field precision")
+        if r.dtype != self.cdtype or r.device != self.device or r.shape[-2:] != (self.n, self.n):
+            raise ValueError(f"r: expected [Q, n, n] in the field precision on {self.device}")
         Q = r.numel() // (self.n * self.n)
         out = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device)
         ws = self.workspace(Q, L.LS_OP_FARFIELD)
@@ -194,8 +204,8 @@ class Context:
                ) -> Tuple[torch.Tensor, List[dict]]:
         f = self._chk_f(f)
         u = self._chk_vol(u, "u")
-        gy = gy.contiguous()
         Q = u.numel() // self.N
+        gy = self._chk_det_q(gy, Q, "gy")
         grad = torch.empty((self.n,) * 3, dtype=self.rdtype, device=self.device)
         ws = self.workspace(Q, L.LS_OP_GRAD) if ws is None else ws
         info = (L.SolveInfo * Q)()
@@ -210,7 +220,7 @@ class Context:
         f = self._chk_f(f)
         d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
         Q = d.shape[0]
-        y_meas = y_meas.contiguous()
+        y_meas = self._chk_det_q(y_meas, Q, "y_meas")
         grad = torch.empty((self.n,) * 3, dtype=self.rdtype, device=self.device)
         ws = self.workspace(Q, L.LS_OP_GRAD) if ws is None else ws
         info = (L.SolveInfo * (2 * Q))()
@@ -224,9 +234,11 @@ class Context:
     def ls_residual(self, y: torch.Tensor, y_meas: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None
                     ) -> Tuple[torch.Tensor, torch.Tensor]:
         """r = y - y_meas and FP64 [||r_q||^2, ||y_meas_q||^2] per illumination."""
-        y, y_meas = y.contiguous(), y_meas.contiguous()
+        y = y.contiguous()
         Q = y.numel() // (self.n * self.n)
-        r = torch.empty_like(y) if out is None else out
+        y = self._chk_det_q(y, Q, "y")
+        y_meas = self._chk_det_q(y_meas, Q, "y_meas")
+        r = torch.empty_like(y) if out is None else self._chk_det_q(out, Q, "out")
         stats = torch.empty(2 * Q, dtype=torch.float64, device=self.device)
         L.check(self.lib.ls_residual(self.h, _ptr(y), _ptr(y_meas), Q, _ptr(r), _ptr(stats), _stream(stream)),
                 "ls_residual")
@@ -234,8 +246,12 @@ class Context:
 
     def ls_grad_accumulate(self, u: torch.Tensor, wb: torch.Tensor, grad: torch.Tensor,
                            stats: Optional[torch.Tensor] = None, accumulate: bool = False, stream=None) -> torch.Tensor:
-        u, wb = self._chk_vol(u, "u"), self._chk_vol(wb, "wb")
+        u = self._chk_vol(u, "u")
         Q = u.numel() // self.N
+        wb = self._chk_like(wb, tuple(u.shape), self.cdtype, "wb")
+        grad = self._chk_f(grad)
+        if stats is not None:
+            stats = self._chk_like(stats, (2 * Q,), torch.float64, "stats")
         L.check(self.lib.ls_grad_accumulate(self.h, _ptr(u), _ptr(wb), Q, _ptr(stats), _ptr(grad),
                                             int(bool(accumulate)), _stream(stream)), "ls_grad_accumulate")
         return grad
@@ -293,6 +309,8 @@ class Context:
             Q = y.numel() // (m * m)
             out = torch.empty((Q, m // q, m // q), dtype=self.cdtype, device=self.device)
         else:
+            if m is None or m % q:
+                raise ValueError("ls_decimate(transpose=True) needs the full detector size m, a multiple of q")
             y = self._chk_det(y.contiguous(), m // q, "y")
             Q = y.numel() // ((m // q) ** 2)
             out = torch.empty((Q, m, m), dtype=self.cdtype, device=self.device)
@@ -303,8 +321,9 @@ class Context:
     def ls_vjp_rhs(self, f: torch.Tensor, u: torch.Tensor, b: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
                    max_restarts: int = 3, ws: Optional[torch.Tensor] = None, stream=None
                    ) -> Tuple[torch.Tensor, List[dict]]:
-        f, u, b = self._chk_f(f), self._chk_vol(u, "u"), self._chk_vol(b.contiguous(), "b")
+        f, u = self._chk_f(f), self._chk_vol(u, "u")
         Q = u.numel() // self.N
+        b = self._chk_like(b.contiguous(), tuple(u.shape), self.cdtype, "b")
         grad = torch.empty((self.n,) * 3, dtype=self.rdtype, device=self.device)
         ws = self.workspace(Q, L.LS_OP_GRAD) if ws is None else ws
         info = (L.SolveInfo * Q)()
@@ -380,6 +399,11 @@ class Batch:
 
     def ls_batch_admit(self, slot: int, f: torch.Tensor, x: torch.Tensor, direction=None,
                        rhs: Optional[torch.Tensor] = None, stream=None) -> None:
+        c, vol = self.ctx, (self.ctx.n,) * 3
+        c._chk_f(f)
+        c._chk_like(x, vol, c.cdtype, "x")
+        if rhs is not None:
+            c._chk_like(rhs, vol, c.cdtype, "rhs")
         dptr = None
         if direction is not None:
             d = np.ascontiguousarray(np.asarray(direction, dtype=np.float64).reshape(3))

@@ -132,3 +132,26 @@ def test_one_context_two_streams_two_threads(c):
     torch.cuda.synchronize()
     assert not errors and not any(t.is_alive() for t in th)
     assert torch.equal(outs[0], refs[0]) and torch.equal(outs[1], refs[1])
+
+
+def test_binding_rejects_mis_sized_buffers(c):
+    # the library sees only pointers: the binding checks every caller buffer before the call, so a
+    # wrong size is a ValueError and never an access outside an allocation
+    n = 32
+    f = torch.zeros((n, n, n), dtype=torch.float32, device=DEV)
+    dirs = workloads.cone_dirs(3, 30.0)
+    with pytest.raises(ValueError):
+        c.ls_forward(f, dirs, u=torch.empty((2, n, n, n), dtype=torch.complex64, device=DEV))   # Q = 3
+    u, _ = c.ls_forward(f, dirs, tol=1e-6)
+    with pytest.raises(ValueError):
+        c.ls_vjp(f, u, torch.zeros((2, n, n), dtype=torch.complex64, device=DEV))
+    with pytest.raises(ValueError):
+        c.ls_grad(f, dirs, torch.zeros((3, n, n), dtype=torch.complex128, device=DEV))          # dtype
+    with pytest.raises(ValueError):
+        c.ls_residual(torch.zeros((3, n, n), dtype=torch.complex64, device=DEV),
+                      torch.zeros((2, n, n), dtype=torch.complex64, device=DEV))
+    with pytest.raises(ValueError):
+        c.ls_grad_accumulate(u, u[:2].contiguous(), torch.zeros((n, n, n), dtype=torch.float32, device=DEV))
+    b = api.Batch(c, 2)
+    with pytest.raises(ValueError):
+        b.ls_batch_admit(0, f, torch.empty((n, n, n - 1), dtype=torch.complex64, device=DEV), direction=[0, 0, 1])
