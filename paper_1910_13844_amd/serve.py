@@ -175,6 +175,73 @@ class Scheduler:
         return summarize(self.completed, total, self.solves)
 
 
+class ConcurrentScheduler(Scheduler):
+    """The same continuous batching with one host thread per slot pool.  Each pool's thread fills,
+    steps and harvests its pool inside ``engine.stream_context(n)`` (for the GPU engine, a stream of
+    its own), so the pools of different grid sizes run on the device at the same time and one
+    pool's host work (admissions, far fields of finished requests) overlaps the others' kernels.
+    All scheduler state is guarded by one lock; the engine's step runs outside it."""
+
+    def run(self, trace: Sequence[Request], realtime: bool = True) -> dict:
+        import contextlib
+        import threading
+
+        trace = sorted(trace, key=lambda r: r.arrival)
+        t0 = self.clock()
+        cv = threading.Condition()
+        state = {"closed": False, "error": None}
+        workers: Dict[int, threading.Thread] = {}
+        stream_context = getattr(self.e, "stream_context", None)
+
+        def pool_busy(n):
+            return any(s is not None for s in self.slots[n]) or bool(self.pending[n])
+
+        def worker(n):
+            try:
+                with (stream_context(n) if stream_context else contextlib.nullcontext()):
+                    while True:
+                        with cv:
+                            while state["error"] is None and not state["closed"] and not pool_busy(n):
+                                cv.wait(0.05)
+                            if state["error"] is not None or (state["closed"] and not pool_busy(n)):
+                                return
+                            self._fill(n)
+                            active = any(s is not None for s in self.slots[n])
+                        if active:
+                            self.e.step(n, self.iters)
+                            with cv:
+                                self._harvest(n, t0)
+                                cv.notify_all()
+            except BaseException as exc:  # reported by run() after the threads have stopped
+                with cv:
+                    state["error"] = exc
+                    cv.notify_all()
+
+        for req in trace:
+            now = self.clock() - t0
+            if realtime and req.arrival > now:
+                time.sleep(req.arrival - now)
+            with cv:
+                if state["error"] is not None:
+                    break
+                self.submit(req)
+                if req.n not in workers:
+                    workers[req.n] = threading.Thread(target=worker, args=(req.n,), daemon=True)
+                    workers[req.n].start()
+                cv.notify_all()
+        with cv:
+            state["closed"] = True
+            cv.notify_all()
+        for w in workers.values():
+            w.join()
+        if state["error"] is not None:
+            raise state["error"]
+        if hasattr(self.e, "synchronize"):
+            self.e.synchronize()
+        total = self.clock() - t0
+        return summarize(self.completed, total, self.solves)
+
+
 def summarize(done: Sequence[Request], total: float, solves: int) -> dict:
     lat = [r.done_time - r.arrival for r in done]
     return {"requests": len(done), "solves": solves, "seconds": total,
@@ -200,9 +267,19 @@ class GpuEngine:
         self.ctx: Dict[int, "api.Context"] = {}
         self.pool: Dict[int, "api.Batch"] = {}
         self.data: Dict[int, dict] = {}
+        self.streams: Dict[int, "torch.cuda.Stream"] = {}
         # request inputs (potential, directions, measurements) keyed by request id; may be shared
         # between engines on the same device so that a trace is generated once
         self.inputs: Dict[int, dict] = {} if inputs is None else inputs
+
+    def stream_context(self, n):
+        """Context manager that makes pool n's own stream current (default priority)."""
+        if n not in self.streams:
+            self.streams[n] = self.torch.cuda.Stream(device=self.device)
+        return self.torch.cuda.stream(self.streams[n])
+
+    def synchronize(self):
+        self.torch.cuda.synchronize(self.device)
 
     def _ctx(self, n):
         if n not in self.ctx:
@@ -282,6 +359,7 @@ class GpuEngine:
         else:
             req.outputs["y"] = d["y"]
             self.data.pop(req.rid, None)
+            self.torch.cuda.current_stream().synchronize()   # the request is complete when its field is
 
     def finish_grad(self, req: Request):
         d = self.data[req.rid]
@@ -290,6 +368,7 @@ class GpuEngine:
         req.outputs["grad"] = c.ls_grad_accumulate(d["u"], d["w"], g, stats=d["stats"])
         req.outputs["loss"] = d["loss"]
         self.data.pop(req.rid, None)
+        self.torch.cuda.current_stream().synchronize()
 
 
 def one_at_a_time(engine_factory, trace: Sequence[Request]) -> dict:
@@ -355,6 +434,8 @@ def main(argv=None) -> int:
     ap.add_argument("--qmax", type=int, default=60)
     ap.add_argument("--budget-gb", type=float, default=120.0)
     ap.add_argument("--baseline", action="store_true", help="also run the one-solve-at-a-time baseline")
+    ap.add_argument("--single-thread", action="store_true",
+                    help="step the slot pools one after the other from one host thread")
     args = ap.parse_args(argv)
     import torch
 
@@ -367,8 +448,9 @@ def main(argv=None) -> int:
     eng.preload(trace)
     print(f"[serve] inputs for {len(trace)} requests ready in {time.perf_counter() - t:.1f} s", file=sys.stderr,
           flush=True)
-    sched = Scheduler(eng, progress=50)
+    sched = (Scheduler if args.single_thread else ConcurrentScheduler)(eng, progress=50)
     res = {"continuous": sched.run(trace)}
+    torch.cuda.synchronize()
     print(f"[serve] continuous: {res['continuous']}", file=sys.stderr, flush=True)
     if args.baseline:
         del sched, eng
@@ -378,6 +460,7 @@ def main(argv=None) -> int:
         res["alone_vs_mix_max_rel"] = _max_rel_diff(trace, trace_b)
     nsolve = sum(r.Q * (2 if r.kind == "grad" else 1) for r in trace)
     res["config"] = {"requests": args.requests, "rate": args.rate, "grids": grids, "qmax": args.qmax,
+                     "scheduler": "single thread" if args.single_thread else "one thread and stream per pool",
                      "solves_in_trace": nsolve, "trace_seconds": max(r.arrival for r in trace)}
     print(json.dumps(res), flush=True)
     return 0

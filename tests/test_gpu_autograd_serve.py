@@ -47,11 +47,13 @@ def test_autograd_gradcheck():
     assert torch.autograd.gradcheck(fn, (f,), eps=1e-6, atol=1e-8, rtol=1e-5, fast_mode=True)
 
 
-def test_served_results_equal_alone():
+@pytest.mark.parametrize("scheduler", ["single", "concurrent"])
+def test_served_results_equal_alone(scheduler):
+    # single: pools stepped one after the other; concurrent: one host thread and stream per pool
     trace = serve.poisson_trace(6, 1000.0, [16, 32], qmax=4, seed=3)
     eng = serve.GpuEngine(hbm_budget_gb=4.0, tol=1e-6, max_slots=5)
     eng.preload(trace)
-    sch = serve.Scheduler(eng, iters_per_step=1)
+    sch = (serve.Scheduler if scheduler == "single" else serve.ConcurrentScheduler)(eng, iters_per_step=1)
     res = sch.run(trace, realtime=False)
     assert res["requests"] == len(trace)
     for r in trace:

@@ -108,3 +108,44 @@ def test_latency_summary():
     reqs = [serve.Request(i, "forward", 16, 1, float(i), i, 45.0, done_time=float(i) + 0.5) for i in range(10)]
     s = serve.summarize(reqs, 10.0, 10)
     assert abs(s["p50_ms"] - 500.0) < 1e-9 and s["solves_per_s"] == 1.0
+
+
+class LockedFakeEngine(FakeEngine):
+    """FakeEngine safe to call from several threads (the concurrent scheduler steps pools in parallel)."""
+
+    def __init__(self, capacity=3):
+        import threading
+        super().__init__(capacity)
+        self._lock = threading.Lock()
+
+    def admit(self, n, slot, job):
+        with self._lock:
+            super().admit(n, slot, job)
+
+    def step(self, n, iters):
+        with self._lock:
+            super().step(n, iters)
+
+    def poll(self, n):
+        with self._lock:
+            return super().poll(n)
+
+    def release(self, n, slot):
+        with self._lock:
+            super().release(n, slot)
+
+
+def test_concurrent_scheduler_completes_the_same_work():
+    # one thread per pool: every request completes, capacities hold, and each request sees its
+    # phases in order, as with the single-threaded loop
+    trace = serve.poisson_trace(16, 50.0, [16, 32, 48], qmax=5, seed=3)
+    eng = LockedFakeEngine(capacity=3)
+    sch = serve.ConcurrentScheduler(eng, iters_per_step=1, clock=eng.clock)
+    res = sch.run(trace, realtime=False)
+    assert res["requests"] == 16
+    assert res["solves"] == sum(r.Q * (2 if r.kind == "grad" else 1) for r in trace)
+    assert all(v <= 3 for v in eng.max_busy.values())
+    assert not eng.running
+    for r in trace:
+        names = [e[0] for e in eng.log if len(e) >= 2 and e[1] == r.rid]
+        assert names.count("ffwd") == 1 and names.count("fgrad") == (1 if r.kind == "grad" else 0)
