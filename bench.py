@@ -134,7 +134,7 @@ def main() -> int:
     # n-point DFTs (z-convolution)] + pointwise kernel products
     import math
     C = {True: {8: 2, 16: 2, 32: 2, 64: 2, 96: 6, 128: 8, 144: 18, 192: 12, 256: 16},
-         False: {8: 2, 16: 2, 32: 2, 64: 2, 96: 2, 128: 4, 144: 18, 192: 6, 256: 8}}[W.precision == "c128"][n]
+         False: {8: 2, 16: 2, 32: 2, 64: 2, 96: 2, 128: 4, 144: 6, 192: 6, 256: 8}}[W.precision == "c128"][n]
     Mc = 2 * n // C
     yz_flops = Q * 2 * n * C * (2 * n * 5 * Mc * math.log2(Mc) + Mc * 4 * 5 * n * math.log2(n)
                                 + 2 * Mc * n * 6)

@@ -152,6 +152,83 @@ __device__ __forceinline__ void fft_group(cplx<T>* base, int stride, int lane, c
 }
 
 // ---------------------------------------------------------------------------------------------
+// 9-point DFT in registers as 3 x 3 (Cooley-Tukey): 3-point DFTs over n1 of x[3 n1 + n2], twiddles
+// exp(DIR 2 pi i n2 k1 / 9), 3-point DFTs over n2; X[k1 + 3 k2].
+template <int DIR, typename T>
+struct SmallDFT<9, DIR, T> {
+  static __device__ __forceinline__ void run(cplx<T>* a) {
+    const T c1 = (T)0.76604444311897803520, s1 = (T)0.64278760968653932632;  // 2 pi / 9
+    const T c2 = (T)0.17364817766693034885, s2 = (T)0.98480775301220805936;  // 4 pi / 9
+    const T c4 = (T)-0.93969262078590838405, s4 = (T)0.34202014332566873304; // 8 pi / 9
+    cplx<T> b[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+      cplx<T> t[3] = {a[n2], a[3 + n2], a[6 + n2]};
+      SmallDFT<3, DIR, T>::run(t);
+      b[n2][0] = t[0];
+      b[n2][1] = t[1];
+      b[n2][2] = t[2];
+    }
+    b[1][1] = b[1][1] * cplx<T>{c1, DIR * s1};
+    b[1][2] = b[1][2] * cplx<T>{c2, DIR * s2};
+    b[2][1] = b[2][1] * cplx<T>{c2, DIR * s2};
+    b[2][2] = b[2][2] * cplx<T>{c4, DIR * s4};
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      cplx<T> t[3] = {b[0][k1], b[1][k1], b[2][k1]};
+      SmallDFT<3, DIR, T>::run(t);
+      a[k1] = t[0];
+      a[k1 + 3] = t[1];
+      a[k1 + 6] = t[2];
+    }
+  }
+};
+
+// 12-point DFT by the prime-factor algorithm, 12 = 3 x 4: input n = (4 n1 + 3 n2) mod 12, 4-point
+// DFTs over n2, 3-point DFTs over n1, output k = (4 k1 + 9 k2) mod 12.
+template <int DIR, typename T>
+struct SmallDFT<12, DIR, T> {
+  static __device__ __forceinline__ void run(cplx<T>* a) {
+    cplx<T> y[3][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+#pragma unroll
+      for (int n2 = 0; n2 < 4; ++n2) y[n1][n2] = a[(4 * n1 + 3 * n2) % 12];
+      SmallDFT<4, DIR, T>::run(y[n1]);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      cplx<T> t[3] = {y[0][k2], y[1][k2], y[2][k2]};
+      SmallDFT<3, DIR, T>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) a[(4 * k1 + 9 * k2) % 12] = t[k1];
+    }
+  }
+};
+
+// 36-point DFT by the prime-factor algorithm, 36 = 4 x 9: input n = (9 n1 + 4 n2) mod 36, 9-point
+// DFTs over n2, 4-point DFTs over n1, output k = (9 k1 + 28 k2) mod 36.
+template <int DIR, typename T>
+struct SmallDFT<36, DIR, T> {
+  static __device__ __forceinline__ void run(cplx<T>* a) {
+    cplx<T> y[4][9];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+#pragma unroll
+      for (int n2 = 0; n2 < 9; ++n2) y[n1][n2] = a[(9 * n1 + 4 * n2) % 36];
+      SmallDFT<9, DIR, T>::run(y[n1]);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 9; ++k2) {
+      cplx<T> t[4] = {y[0][k2], y[1][k2], y[2][k2], y[3][k2]};
+      SmallDFT<4, DIR, T>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[(9 * k1 + 28 * k2) % 36] = t[k1];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------------------
 // 24-point DFT in registers by the prime-factor (Good-Thomas) algorithm, 24 = 3 x 8 with 3 and 8
 // coprime, so no twiddles: input n = (8 n1 + 3 n2) mod 24, 8-point DFTs over n2, 3-point DFTs over
 // n1, output k = (16 k1 + 9 k2) mod 24 (k = k1 mod 3, k = k2 mod 8).  Index maps are
@@ -227,6 +304,8 @@ template <> struct Split<128> { static constexpr int L = 8, E = 16; };
 template <> struct Split<256> { static constexpr int L = 16, E = 16; };
 template <> struct Split<96>  { static constexpr int L = 4, E = 24; };
 template <> struct Split<192> { static constexpr int L = 8, E = 24; };
+template <> struct Split<48>  { static constexpr int L = 4, E = 12; };
+template <> struct Split<144> { static constexpr int L = 4, E = 36; };
 
 template <int N>
 __device__ __forceinline__ int tpos(int k1, int m) {

@@ -89,8 +89,8 @@ __device__ __forceinline__ double* part_ptr(const PassArgs& a, int slot, int blk
 // the storage order of bpos() (natural order for the Stockham sizes).
 template <int N>
 struct HasSplit {
-  static constexpr bool value = (N == 8 || N == 16 || N == 32 || N == 64 || N == 96 || N == 128 || N == 192 ||
-                                 N == 256);
+  static constexpr bool value = (N == 8 || N == 16 || N == 32 || N == 48 || N == 64 || N == 96 || N == 128 ||
+                                 N == 192 || N == 256);
 };
 
 template <typename T, int N, int DIR, int TWS = 2>
@@ -861,7 +861,7 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
 template <typename T, int N>
 struct ClassCfg {
   // number of classes; 2 = k_yz3
-  static constexpr int C = N == 144 ? 18
+  static constexpr int C = N == 144 ? (sizeof(T) == 4 ? 6 : 18)
                           : sizeof(T) == 4 ? (N <= 96 ? 2 : (N == 128 ? 4 : (N == 192 ? 6 : 8)))
                                            : (N <= 64 ? 2 : (N == 96 ? 6 : (N == 128 ? 8 : (N == 192 ? 12 : 16))));
   static constexpr int M = 2 * N / C;
@@ -870,10 +870,11 @@ struct ClassCfg {
   static constexpr int NT = (sizeof(T) == 4 && N >= 192) ? 512 : 256;
   // waves per SIMD the register allocation must leave room for (complex128 at 128: two workgroups
   // per CU at the price of a few spilled registers)
-  static constexpr int WPE = (sizeof(T) == 8 && N == 128) ? 2 : 1;
+  static constexpr int WPE = ((sizeof(T) == 8 && N == 128) || (sizeof(T) == 4 && N == 144)) ? 2 : 1;
   // z-convolution by the register four-step transform (else the in-LDS Stockham one; complex128
-  // at 96 keeps the latter, which needs fewer registers)
-  static constexpr bool ZFOUR = HasSplit<N>::value && !(sizeof(T) == 8 && N == 96);
+  // at 96 and 144 keeps the latter, which needs fewer registers).  144 = 4 x 36 is split for the
+  // z-convolution only; its row transforms elsewhere stay Stockham.
+  static constexpr bool ZFOUR = (HasSplit<N>::value || N == 144) && !(sizeof(T) == 8 && (N == 96 || N == 144));
   static constexpr int PITCH = M + 1;
   static_assert(C == 2 || (HasSplit<M>::value && N % M == 0 && M % 16 == 0), "class slab shape");
 };
@@ -896,7 +897,7 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
   __shared__ cplx<T> slab[N * PITCH];
   __shared__ cplx<T> tw[2 * N];
   __shared__ cplx<T> twlM[M];
-  __shared__ cplx<T> twlN[twl_size<N>()];
+  __shared__ cplx<T> twlN[CC::ZFOUR ? N : 1];
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   // consecutive blocks on one XCD: the C classes of one (kx, slot) plane (the plane is read once
@@ -918,7 +919,7 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
     const char* plane0 = (const char*)Sv + soff * sizeof(cplx<T>);
     constexpr int PER = N * M / NT;
     constexpr int CH0 = 32 / F < 8 ? 32 / F : 8;  // at most 32 loads in flight per thread
-    constexpr int CH = PER % CH0 == 0 ? CH0 : (PER % 4 == 0 ? 4 : (PER % 2 == 0 ? 2 : 1));
+    constexpr int CH = largest_divisor_upto(PER, CH0);
     static_assert(PER % CH == 0 && PER * NT == N * M, "fold chunks");
     for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
 #pragma unroll 1
@@ -945,7 +946,7 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
     }
   }
   fill_twl_stride<T, M, C>(twlM, tw, tid, NT);
-  fill_twl_any<T, N>(twlN, tw, tid, NT);
+  if constexpr (CC::ZFOUR) fill_twl<T, N>(twlN, tw, tid, NT);
   __syncthreads();
   {
     constexpr int G = NT / LM;
