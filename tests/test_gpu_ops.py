@@ -94,3 +94,21 @@ def test_farfield_adjoint(n, prec, tol):
         ref = farfield.farfield_T(r[q], K, float(n))
         assert rel(out[q], ref) < tol
         assert rel(outc[q], farfield.farfield_T(np.conj(r[q]), K, float(n))) < tol
+
+
+@pytest.mark.parametrize("n,prec,tol", [(16, "c128", 1e-13), (32, "c128", 1e-13), (32, "c64", 1e-6)])
+def test_impulse_response_is_the_modified_kernel(n, prec, tol):
+    # G applied to a unit impulse at the origin voxel returns the Proposition 2 kernel itself:
+    # (G delta)[k] = gm[k] for every k in Omega_n (signed positions -n/2+1 .. n/2), a direct check of
+    # the kernel the GPU built against oracle.kernel.gm_coset, value by value
+    c = ctx(n, prec)
+    o = n // 2 - 1                                   # array index of position 0
+    v = torch.zeros((1, n, n, n), dtype=cdt(prec), device=DEV)
+    v[0, o, o, o] = 1.0
+    out = c.ls_apply_G(v)[0].cpu().numpy()
+    gm = kernel.gm_coset(n, 4, K)                    # (2n)^3, indices taken mod 2n
+    pos = np.arange(n) - o
+    ref = gm[np.ix_(pos % (2 * n), pos % (2 * n), pos % (2 * n))]
+    e = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"[impulse] n={n} {prec}: max |G delta - gm| / max |gm| = {e:.2e}", flush=True)
+    assert e < tol
