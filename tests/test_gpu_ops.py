@@ -112,3 +112,26 @@ def test_impulse_response_is_the_modified_kernel(n, prec, tol):
     e = np.abs(out - ref).max() / np.abs(ref).max()
     print(f"[impulse] n={n} {prec}: max |G delta - gm| / max |gm| = {e:.2e}", flush=True)
     assert e < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-13), ("c64", 1e-6)])
+def test_far_field_of_one_voxel_is_the_green_function(prec, tol):
+    # a single scattering voxel at (z0, y0, x0): y[a] = g(x_a - x0, y_a - y0, x_Gamma - z0) with the
+    # untruncated g = exp(i k r) / (4 pi r) (eq. (lipp2)), a direct check of the far-field kernels
+    from oracle import green
+    n = 16
+    c = ctx(n, prec)
+    z0, y0, x0 = 3, 9, 12
+    f = np.zeros((n, n, n))
+    f[z0, y0, x0] = 1.0
+    rd = torch.float64 if prec == "c128" else torch.float32
+    u = torch.ones((1, n, n, n), dtype=cdt(prec), device=DEV)
+    y = c.ls_farfield(torch.from_numpy(f).to(DEV, rd), u)[0].cpu().numpy()
+    pos = np.arange(n) - n // 2 + 1.0
+    dy = pos[:, None] - pos[y0]
+    dx = pos[None, :] - pos[x0]
+    r = np.sqrt(dx ** 2 + dy ** 2 + (float(n) - pos[z0]) ** 2)
+    ref = green.g_free(r, K)
+    e = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"[voxel] {prec}: max |y - g| / max |g| = {e:.2e}", flush=True)
+    assert e < tol
