@@ -103,3 +103,29 @@ def test_born_limit_is_second_order():
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
     for e, g, i, gi in zip(errs, gold["err"], iters, gold["iters"]):
         assert abs(e - g) <= 1e-9 * g and abs(i - gi) <= 1
+
+
+def test_G_converges_to_the_continuous_convolution():
+    # Theorem 1's accuracy statement on the GPU: a radial bump (1 - |x|^2/a^2)^4 in a cube of side
+    # L = 8 sampled at n = 32, 64, 128 (complex128); h^2 G v at grid points approaches the exact
+    # continuous convolution with g (Helmholtz shell theorem, oracle.bump) as n grows
+    from oracle import bump
+    L, kb, a, q = 8.0, 1.3, 2.8, 4
+    pts = [(0.0, 0.0, 0.0), (1.0, 1.0, -1.0), (2.0, -1.0, 1.0)]
+    refs = [bump.conv_exact(float(np.sqrt(x * x + y * y + z * z)), kb, a, q) for (x, y, z) in pts]
+    errs = []
+    for n in (32, 64, 128):
+        h = L / n
+        c = api.Context(n, kb * h, p=4, xg=float(n), prec="c128", device=DEV)
+        cc = (np.arange(n) - n // 2 + 1) * h
+        Z, Y, X = np.meshgrid(cc, cc, cc, indexing="ij")
+        v = torch.from_numpy(bump.bump(np.sqrt(X ** 2 + Y ** 2 + Z ** 2), a, q).astype(np.complex128)).to(DEV)
+        Gv = (h * h) * c.ls_apply_G(v[None].contiguous())[0]
+        e = 0.0
+        for (x, y, z), ref in zip(pts, refs):
+            i = tuple(int(round(t / h)) + n // 2 - 1 for t in (z, y, x))
+            e = max(e, abs(complex(Gv[i].item()) - ref) / abs(ref))
+        errs.append(e)
+        del c
+    print(f"[theorem 1] bump, max relative error at n = 32, 64, 128: {errs}", flush=True)
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-7
