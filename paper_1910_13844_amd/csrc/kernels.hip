@@ -934,14 +934,42 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
           xv[k][m] = ldo<T>(plane0, (uint32_t)(zz * N + j + m * M) * (uint32_t)sizeof(cplx<T>));
       }
       if (k0 == 0) __syncthreads();  // tw visible
+      // sum_m x_m exp(-i pi c (j + m M) / n) = exp(-i pi c j / n) sum_m x_m rho^m with
+      // rho = exp(-2 pi i c / C): one table twiddle per point; for C = 4, rho is a power of -i
+      cplx<T> rho[F];
 #pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        const int idx = tid + (k0 + k) * NT;
-        const int zz = idx / M, j = idx - zz * M;
-        cplx<T> acc = c == 0 ? xv[k][0] : xv[k][0] * tw[(c * j) % (2 * N)];
+      for (int m = 1; m < F; ++m) rho[m] = tw[(c * m * M) % (2 * N)];
+      // one loop per class value for C = 4 (the branch is uniform), so the multiplication by the
+      // power of -i is a register permutation
+      auto fold = [&](auto rc) {
+        constexpr int RC = decltype(rc)::value;
 #pragma unroll
-        for (int m = 1; m < F; ++m) acc = acc + xv[k][m] * tw[(c * (j + m * M)) % (2 * N)];
-        slab[zz * PITCH + j] = acc;
+        for (int k = 0; k < CH; ++k) {
+          const int idx = tid + (k0 + k) * NT;
+          const int zz = idx / M, j = idx - zz * M;
+          cplx<T> acc = xv[k][0];
+          if constexpr (C == 4 && F == 2) {
+            const cplx<T> x1 = xv[k][1];
+            acc = RC == 0 ? acc + x1 : (RC == 1 ? acc + mul_i<-1>(x1) : (RC == 2 ? acc - x1 : acc + mul_i<+1>(x1)));
+          } else {
+#pragma unroll
+            for (int m = 1; m < F; ++m) acc = acc + xv[k][m] * rho[m];
+          }
+          if (c != 0) acc = acc * tw[(c * j) % (2 * N)];
+          slab[zz * PITCH + j] = acc;
+        }
+      };
+      if constexpr (C == 4 && F == 2) {
+        if (c == 0)
+          fold(std::integral_constant<int, 0>{});
+        else if (c == 1)
+          fold(std::integral_constant<int, 1>{});
+        else if (c == 2)
+          fold(std::integral_constant<int, 2>{});
+        else
+          fold(std::integral_constant<int, 3>{});
+      } else {
+        fold(std::integral_constant<int, 0>{});
       }
     }
   }
