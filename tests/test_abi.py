@@ -68,3 +68,36 @@ def test_null_context_rejected(lib):
     assert lib.ls_workspace_bytes(None, 4, 0, C.byref(b)) == -1
     assert lib.ls_forward(None, None, 1, None, None, None, None, None, 0, None) == -1
     assert lib.ls_strerror(-2).decode().startswith("workspace")
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes structures mirror include/ls.h: compile the header with the host C compiler and
+    # compare sizes and field offsets
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stddef.h>
+#include <stdio.h>
+#include "ls.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(ls_geom), offsetof(ls_geom, kbh), offsetof(ls_geom, xg), offsetof(ls_geom, prec));
+  printf("%zu %zu %zu\\n", sizeof(ls_solve_opts), offsetof(ls_solve_opts, maxit), offsetof(ls_solve_opts, max_restarts));
+  printf("%zu %zu %zu %zu\\n", sizeof(ls_solve_info), offsetof(ls_solve_info, relres_rec),
+         offsetof(ls_solve_info, relres_true), offsetof(ls_solve_info, time_ms));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    g = [int(t) for t in lines[0].split()]
+    o = [int(t) for t in lines[1].split()]
+    i = [int(t) for t in lines[2].split()]
+    assert g == [C.sizeof(L.Geom), L.Geom.kbh.offset, L.Geom.xg.offset, L.Geom.prec.offset]
+    assert o == [C.sizeof(L.SolveOpts), L.SolveOpts.maxit.offset, L.SolveOpts.max_restarts.offset]
+    assert i == [C.sizeof(L.SolveInfo), L.SolveInfo.relres_rec.offset, L.SolveInfo.relres_true.offset,
+                 L.SolveInfo.time_ms.offset]
