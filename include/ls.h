@@ -55,6 +55,10 @@ typedef struct {
   double tol;           /* stop when ||b - A x|| / ||b|| <= tol (recursive residual, re-checked in FP64) */
   int32_t maxit;        /* iteration cap per illumination */
   int32_t max_restarts; /* restarts allowed after breakdown or a failed true-residual check */
+  int32_t x0_mode;      /* initial guess of ls_forward / ls_forward_uin: 0 x0 = u_in (the incident
+                           field), 1 x0 = the contents of u on entry (warm start, e.g. the fields of
+                           the previous reconstruction iterate); other calls use x0 = b */
+  int32_t reserved;     /* 0 */
 } ls_solve_opts;
 
 typedef struct {

@@ -33,7 +33,8 @@ class Geom(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("max_restarts", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("max_restarts", C.c_int32), ("x0_mode", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

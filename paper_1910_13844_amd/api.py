@@ -105,8 +105,8 @@ class Context:
         return self._chk_like(y.contiguous(), (Q, self.n, self.n), self.cdtype, name)
 
     @staticmethod
-    def _opts(tol: float, maxit: int, max_restarts: int) -> L.SolveOpts:
-        return L.SolveOpts(float(tol), int(maxit), int(max_restarts))
+    def _opts(tol: float, maxit: int, max_restarts: int, x0_mode: int = 0) -> L.SolveOpts:
+        return L.SolveOpts(float(tol), int(maxit), int(max_restarts), int(x0_mode), 0)
 
     # -- operators -------------------------------------------------------------------------
     def ls_apply_G(self, v: torch.Tensor, stream=None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -128,9 +128,13 @@ class Context:
         return out
 
     def ls_forward(self, f: torch.Tensor, dirs, tol: float = 1e-5, maxit: int = 500, max_restarts: int = 3,
-                   u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None
-                   ) -> Tuple[torch.Tensor, List[dict]]:
+                   u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None,
+                   warm_start: bool = False) -> Tuple[torch.Tensor, List[dict]]:
+        """Forward solves for plane waves `dirs`.  warm_start: start BiCGSTAB from the contents of
+        `u` (which must then be given) instead of from the incident field."""
         f = self._chk_f(f)
+        if warm_start and u is None:
+            raise ValueError("warm_start needs u (the initial guesses)")
         d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
         Q = d.shape[0]
         if u is None:
@@ -138,16 +142,18 @@ class Context:
         self._chk_like(u, (Q, self.n, self.n, self.n), self.cdtype, "u")
         ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
         info = (L.SolveInfo * Q)()
-        o = self._opts(tol, maxit, max_restarts)
+        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0)
         L.check(self.lib.ls_forward(self.h, _ptr(f), Q, d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(u),
                                     C.byref(o), info, _ptr(ws), ws.numel(), _stream(stream)), "ls_forward")
         return u, [i.as_dict() for i in info]
 
     def ls_forward_uin(self, f: torch.Tensor, uin: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
                        max_restarts: int = 3, u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-                       stream=None) -> Tuple[torch.Tensor, List[dict]]:
-        """Forward solves with stored incident volumes uin [Q, n, n, n]."""
+                       stream=None, warm_start: bool = False) -> Tuple[torch.Tensor, List[dict]]:
+        """Forward solves with stored incident volumes uin [Q, n, n, n] (warm_start as in ls_forward)."""
         f = self._chk_f(f)
+        if warm_start and u is None:
+            raise ValueError("warm_start needs u (the initial guesses)")
         uin = self._chk_vol(uin, "uin")
         Q = uin.numel() // self.N
         if u is None:
@@ -155,7 +161,7 @@ class Context:
         self._chk_like(u, tuple(uin.shape), self.cdtype, "u")
         ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
         info = (L.SolveInfo * Q)()
-        o = self._opts(tol, maxit, max_restarts)
+        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0)
         L.check(self.lib.ls_forward_uin(self.h, _ptr(f), Q, _ptr(uin), _ptr(u), C.byref(o), info, _ptr(ws), ws.numel(),
                                         _stream(stream)), "ls_forward_uin")
         return u, [i.as_dict() for i in info]

@@ -108,6 +108,7 @@ struct Run {
   const ls_ctx* c;
   hipStream_t s;
   int nslots;
+  bool warm = false;  // x0 = the contents of vec[V_X] (else x0 = b)
   SlotDesc* d_desc;
   SlotState* d_st;
   double* d_part;
@@ -166,7 +167,11 @@ int scalar(const Run& r, int kind, uint32_t mask) {
 int enqueue_steps(const Run& r, int iters, bool init) {
   int rc;
   if (init) {
-    if ((rc = matvec(r, PRO_F_B, 0, EPI_R0, 0, 0, M_INIT))) return rc;
+    if (r.warm) {
+      if ((rc = matvec(r, PRO_F_VEC, V_X, EPI_R0X, 0, 0, M_INIT))) return rc;
+    } else {
+      if ((rc = matvec(r, PRO_F_B, 0, EPI_R0, 0, 0, M_INIT))) return rc;
+    }
     if ((rc = scalar(r, SC_INIT, M_INIT))) return rc;
   }
   for (int it = 0; it < iters; ++it) {
@@ -251,6 +256,7 @@ SlotState run_state() {
   o.tol = 1e-5;
   o.maxit = 1;
   o.max_restarts = 0;
+  o.x0_mode = 0;
   return init_state(&o, ST_RUN);
 }
 
@@ -259,11 +265,14 @@ ls_solve_opts opts_or_default(const ls_solve_opts* o) {
   d.tol = 1e-5;
   d.maxit = 500;
   d.max_restarts = 3;
+  d.x0_mode = 0;
   if (o) d = *o;
   return d;
 }
 
-bool opts_ok(const ls_solve_opts& o) { return o.tol > 0.0 && std::isfinite(o.tol) && o.maxit >= 1 && o.max_restarts >= 0; }
+bool opts_ok(const ls_solve_opts& o) {
+  return o.tol > 0.0 && std::isfinite(o.tol) && o.maxit >= 1 && o.max_restarts >= 0 && (o.x0_mode == 0 || o.x0_mode == 1);
+}
 
 char* vptr(const ls_ctx* c, char* ws, const WsLayout& L, int slot, int k) {
   return ws + L.off_vec + (size_t)slot * L.per_slot + (size_t)k * c->N * c->csz;
@@ -622,6 +631,7 @@ static int forward_common(const ls_ctx* c, const void* f, int32_t Q, const doubl
         for (int j = 0; j < 3; ++j) d[i].d[j] = dirs[3 * (q0 + i) + j];
     }
     Run r = make_run(c, w, L, nq, 0, s);
+    r.warm = o.x0_mode == 1;
     int rc = upload(r, d, &st);
     if (rc) return rc;
     if ((rc = solve_all(r, h))) return rc;

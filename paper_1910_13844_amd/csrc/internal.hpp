@@ -71,7 +71,8 @@ enum Epi : int {
   EPI_AXT = 2,    // t = s - g, partials <t, s>, ||t||^2
   EPI_R0 = 3,     // x = b, r = rh = g, partials ||g||^2, ||b||^2
   EPI_TRUE = 4,   // r = b - x + g, partial ||r||^2
-  EPI_AX = 5      // vec[sel2] = vec[sel] - g
+  EPI_AX = 5,     // vec[sel2] = vec[sel] - g
+  EPI_R0X = 6     // warm start (x given): r = rh = b - x + g, partials ||r||^2, ||b||^2
 };
 
 struct PassArgs {

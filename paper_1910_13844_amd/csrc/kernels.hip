@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
         q0[it] = ld<T>(d.vec[V_S], idx);
       } else if constexpr (EPI == EPI_R0) {
         if (d.vec[V_B]) q0[it] = ld<T>(d.vec[V_B], idx);
-      } else if constexpr (EPI == EPI_TRUE) {
+      } else if constexpr (EPI == EPI_TRUE || EPI == EPI_R0X) {
         if (d.vec[V_B]) q0[it] = ld<T>(d.vec[V_B], idx);
         q1[it] = ld<T>(d.vec[V_X], idx);
       } else if constexpr (EPI == EPI_AX) {
@@ -477,12 +477,19 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
         const cplx<T> r = (b - q1[it]) + g;
         stv<T>(d.vec[V_R], idx, r);
         a0.re += (double)r.re * r.re + (double)r.im * r.im;
+      } else if constexpr (EPI == EPI_R0X) {
+        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, y0 + yy, x);
+        const cplx<T> r = (b - q1[it]) + g;
+        stv<T>(d.vec[V_R], idx, r);
+        stv<T>(d.vec[V_RH], idx, r);
+        a0.re += (double)r.re * r.re + (double)r.im * r.im;
+        a1.re += (double)b.re * b.re + (double)b.im * b.im;
       } else {  // EPI_AX
         stv<T>(d.vec[a.sel2], idx, q0[it] - g);
       }
     }
   }
-  if constexpr (EPI == EPI_AXV || EPI == EPI_AXT || EPI == EPI_R0 || EPI == EPI_TRUE) {
+  if constexpr (EPI == EPI_AXV || EPI == EPI_AXT || EPI == EPI_R0 || EPI == EPI_R0X || EPI == EPI_TRUE) {
     double v[6] = {a0.re, a0.im, a1.re, a1.im, a2.re, a2.im};
     block_sum<6>(v, red);
     if (tid == 0) {
@@ -490,7 +497,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
         double* pp = part_ptr(a, slot, blk, 0);
         pp[0] = v[0];
         pp[1] = v[1];
-      } else if constexpr (EPI == EPI_R0) {
+      } else if constexpr (EPI == EPI_R0 || EPI == EPI_R0X) {
         double* pp = part_ptr(a, slot, blk, 0);
         pp[0] = v[0];
         pp[1] = 0.0;
@@ -1432,6 +1439,7 @@ static hipError_t xinv_t(const PassArgs& a, hipStream_t s) {
     case EPI_AXT: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXT, CL>), nb, dim3(256), 0, s, a); break;
     case EPI_R0: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0, CL>), nb, dim3(256), 0, s, a); break;
     case EPI_TRUE: hipLaunchKernelGGL((k_xinv<T, N, EPI_TRUE, CL>), nb, dim3(256), 0, s, a); break;
+    case EPI_R0X: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0X, CL>), nb, dim3(256), 0, s, a); break;
     case EPI_AX: hipLaunchKernelGGL((k_xinv<T, N, EPI_AX, CL>), nb, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }

@@ -209,3 +209,29 @@ def test_slot_pool_alone_equals_in_mix():
         bt.ls_batch_release(0)
         st, _ = bt.ls_batch_poll()
         assert st[0] == 0
+
+
+def test_warm_start_follows_the_oracle_from_the_same_initial_guess():
+    # x0_mode = 1: BiCGSTAB starts from the contents of u.  complex128: the same iterate sequence
+    # as oracle.solver.bicgstab(x0 = the same guess); complex64 started from the tightly solved
+    # oracle solution: accepted by the initial residual check, no iteration
+    n = 16
+    f = workloads.blob_potential(2, n, dn_max=0.1)
+    d = workloads.cone_dirs(1, 30.0)
+    b = incident.plane_wave(n, K, d[0])
+    x0 = b + 0.2 * workloads.random_field(21, (n, n, n))
+    c = ctx(n, "c128")
+    u = torch.from_numpy(x0[None].copy()).to(DEV)
+    u, info = c.ls_forward(torch.from_numpy(f).to(DEV), d, tol=1e-10, u=u, warm_start=True)
+    uo, io = solver.bicgstab(lambda v: ops.A_apply(ghat(n), f, v), b, 1e-10, x0=x0)
+    print(f"[warm] c128: {info[0]['iters']} iterations (oracle {io.iters}), "
+          f"difference {rel(u[0].cpu().numpy(), uo):.2e}", flush=True)
+    assert info[0]["status"] == 0 and info[0]["iters"] == io.iters
+    assert rel(u[0].cpu().numpy(), uo) < 1e-10
+    # from the solution itself
+    ut, _ = solver.bicgstab(lambda v: ops.A_apply(ghat(n), f, v), b, 1e-13)
+    c64 = ctx(n, "c64")
+    u32 = torch.from_numpy(ut[None].astype(np.complex64)).to(DEV)
+    u32, i32 = c64.ls_forward(torch.from_numpy(f.astype(np.float32)).to(DEV), d, tol=1e-5, u=u32, warm_start=True)
+    assert i32[0]["status"] == 0 and i32[0]["iters"] == 0 and i32[0]["relres_true"] < 1e-5
+    assert rel(u32[0].cpu().numpy(), ut) < 1e-6
