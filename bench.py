@@ -249,6 +249,20 @@ def data_description(W):
             f"{W.theta_deg:g}-degree cone)")
 
 
+def host_description():
+    """The host the oracle is timed on: logical CPUs visible to this process and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
 def cpu_baseline(W, f_np, dirs, u, mv_per_solve, per_step=1, grad_mode=False):
     """The FP64 oracle timed on the host: one application of A = I - G diag f at the full size
     (two FFTs of (2n)^3) and one far field, scaled by the matvecs per solve of the GPU run.  The
@@ -274,12 +288,12 @@ def cpu_baseline(W, f_np, dirs, u, mv_per_solve, per_step=1, grad_mode=False):
     per_solve = t_mv * mv_per_solve + t_ff
     if grad_mode:   # one gradient = per_step solves (forward and adjoint of every view)
         base = {"value": round(1.0 / (per_solve * per_step), 8), "unit": "gradients/s", "cores": 1, "kind": "oracle",
-                "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
+                "host": host_description(), "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
                            f"{t_ff:.2f} s, scaled by {mv_per_solve:.1f} matvecs/solve x {per_step} solves/gradient; "
                            f"kernel setup {t_setup:.1f} s excluded")}
         return base, {"oracle_relres_q0": relres, "tol": W.tol}
     base = {"value": round(1.0 / per_solve, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
+            "host": host_description(), "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
                        f"{t_ff:.2f} s, scaled by {mv_per_solve:.1f} matvecs/solve; kernel setup {t_setup:.1f} s "
                        "excluded")}
     check = {"oracle_relres_q0": relres, "tol": W.tol}
