@@ -115,3 +115,57 @@ def test_reconstruction_reduces_loss_c64():
     # iterations cut the subset loss by ~8x and the error to the true potential to ~0.57
     assert hist[-1]["loss_at_v"] < 0.2 * hist[0]["loss_at_v"]
     assert err < 0.8
+
+
+@pytest.mark.parametrize("warm_adjoint", [False, True])
+def test_warm_started_loop_matches_oracle(warm_adjoint):
+    # warm starts change where each BiCGSTAB run begins, not what it converges to: with solves to
+    # 1e-12 the loop still follows the oracle's cold-started loop to the same bar
+    n, Q = 8, 6
+    f0, ft = workloads.perturbed_potential(n)
+    dirs = workloads.cone_dirs(Q, 40.0)
+    prob = ograd.Problem(kernel.ghat_m(n, 4, K), n, K, float(n), tol=1e-12)
+    _, y = prob.forward(ft, dirs)
+    subs = workloads.view_subsets(Q, 3, 4, seed=7)
+    tau, gamma0, tv_iters = 1e-4, 30.0, 30
+    hist_o = []
+    fo = orecon.reconstruct(prob, dirs, list(y), np.zeros((n, n, n)), tau, gamma0, subs, tv_iters, history=hist_o)
+    c = ctx(n, "c128")
+    hists = {}
+    for warm in (True, False):
+        hists[warm] = []
+        fg = recon.reconstruct(c, dirs, torch.from_numpy(y).to(DEV),
+                               torch.zeros((n,) * 3, dtype=torch.float64, device=DEV), tau, gamma0, subs, tv_iters,
+                               tol=1e-12, history=hists[warm], warm_start=warm, warm_adjoint=warm_adjoint)
+        if warm:
+            e = rel(fg.cpu().numpy(), fo)
+    print(f"[recon warm] n={n} oracle vs GPU after {len(subs)} iterations: {e:.2e}; loss warm "
+          f"{[round(h['loss_at_v'], 8) for h in hists[True]]}, cold {[round(h['loss_at_v'], 8) for h in hists[False]]}",
+          flush=True)
+    assert e < 1e-9
+    for hw, hc in zip(hists[True], hists[False]):
+        assert abs(hw["loss_at_v"] - hc["loss_at_v"]) <= 1e-9 * hc["loss_at_v"]
+
+
+def test_warm_started_loop_c64_saves_iterations():
+    n, Q = 32, 12
+    c = ctx(n, "c64")
+    _, ft = workloads.perturbed_potential(n)
+    dirs = workloads.cone_dirs(Q, 40.0)
+    ftt = torch.from_numpy(ft).to(DEV, torch.float32)
+    u, _ = c.ls_forward(ftt, dirs, tol=1e-6)
+    y = c.ls_farfield(ftt, u)
+    subs = workloads.view_subsets(Q, 4, 30, seed=3)
+    runs = {}
+    for warm in (False, True):
+        hist = []
+        f = recon.reconstruct(c, dirs, y, torch.zeros_like(ftt), 1e-4, 30.0, subs, 40, history=hist, warm_start=warm)
+        # forward solves are the first half of each iteration's solve records
+        runs[warm] = (f, hist, float(np.mean([np.mean(h["iters"][:len(h["views"])]) for h in hist[1:]])))
+    d = (runs[True][0] - runs[False][0]).norm().item() / runs[False][0].norm().item()
+    print(f"[recon warm c64] mean forward BiCGSTAB iterations after the first step: cold {runs[False][2]:.2f}, "
+          f"warm {runs[True][2]:.2f}; warm vs cold f after {len(subs)} iterations {d:.2e}", flush=True)
+    # both loops solve to 1e-5: single gradients then differ by up to ~1e-3 relative (the same
+    # size as the FP32 against FP64 gradient difference at this tolerance)
+    assert d < 5e-3
+    assert runs[True][2] < runs[False][2]
