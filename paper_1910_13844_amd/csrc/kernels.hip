@@ -311,17 +311,34 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
 
 // =============================================================================================
 // k_xinv: inverse x-DFTs (even + modulated odd half), crop to n, epilogue and FP64 partials.
+// Threads per workgroup: complex64 tiles (2 x 16 rows of n + 1 values) above 56 KB leave room for
+// two workgroups per CU only, so they get 512 threads (16 waves per CU instead of 8 keep more
+// loads in flight) with registers for 4 waves per SIMD; complex128 keeps 256 threads (its
+// register sets would spill at that occupancy).
+template <typename T, int N>
+struct XInvCfg {
+  static constexpr bool WIDE = sizeof(T) == 4 && 2 * XCfg<N>::TY * XCfg<N>::PITCH * (int)sizeof(cplx<T>) > 56 * 1024;
+  static constexpr int NT = WIDE ? 512 : 256;
+  static constexpr int WPE = WIDE ? 4 : 1;
+  static constexpr int IT = (XCfg<N>::TY * N + NT - 1) / NT;
+  static constexpr int IT2 = (2 * N * XCfg<N>::TY + NT - 1) / NT;
+  // outputs per thread handled in one chunk of the class sum (three chunk-sized register sets)
+  static constexpr int ITC_MAX = WIDE ? 8 : (sizeof(T) == 4 ? 16 : 8);
+};
+
 template <typename T, int N, int EPI, int CL>
-__global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
+__global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_xinv(PassArgs a) {
   using X = XCfg<N>;
-  constexpr int TY = X::TY, NYT = X::NYT, PITCH = X::PITCH, IT = X::IT, IT2 = X::IT2;
+  using XI = XInvCfg<T, N>;
+  constexpr int NTX = XI::NT;
+  constexpr int TY = X::TY, NYT = X::NYT, PITCH = X::PITCH, IT = XI::IT, IT2 = XI::IT2;
   constexpr int L = row_lanes<N>();
-  constexpr int NG = 256 / L;
+  constexpr int NG = NTX / L;
   __shared__ cplx<T> bufE[TY * PITCH];
   __shared__ cplx<T> bufO[TY * PITCH];
   __shared__ cplx<T> tw[2 * N];
   __shared__ cplx<T> twl[twl_size<N>()];
-  __shared__ double red[6 * 4];
+  __shared__ double red[6 * (NTX / 64)];
   const int tid = threadIdx.x;
   // CL = 1: plain x-spectrum [kx][z][y].  CL > 1: class-major output of the (y,z) pass,
   // [c][kx][z][j] with rows of CM = 2n / CL (periodic in y with period CM); the value at y is
@@ -347,7 +364,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   const int blk = z * NYT + tr;
   const int y0 = ((tr / FA) + (tr % FA) * TPP) * TY;
   const SlotDesc& d = a.desc[slot];
-  for (int i = tid; i < 2 * N; i += 256) tw[i] = ld<T>(a.tw, i);
+  for (int i = tid; i < 2 * N; i += NTX) tw[i] = ld<T>(a.tw, i);
   {
     static_assert(CL == 1 || (CM % TY == 0 && CL % 2 == 0), "y tiles must stay inside one period");
     const void* spec = d.vec[a.spec];
@@ -355,16 +372,16 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
     // byte offset of (kx, z, j0 + yy) inside one class block; class blocks are 2n nz CM apart
     const size_t cstride = (size_t)2 * N * a.nz * CM * sizeof(cplx<T>);
     const uint32_t off0 = (uint32_t)(((tid / TY) * a.nz + z) * CM + j0 + tid % TY) * (uint32_t)sizeof(cplx<T>);
-    constexpr uint32_t OFF_IT = (256 / TY) * CM * sizeof(cplx<T>);  // per it: 256 / TY more kx
+    constexpr uint32_t OFF_IT = (NTX / TY) * CM * sizeof(cplx<T>);  // per it: NTX / TY more kx
     // outputs are handled in chunks of ITC per thread so that three chunk-sized register sets
     // (sum, current class, next class) fit beside the rest of the kernel
-    constexpr int ITC = largest_divisor_upto(IT2, sizeof(T) == 4 ? 16 : 8);
+    constexpr int ITC = largest_divisor_upto(IT2, XI::ITC_MAX);
     auto load = [&](cplx<T>(&v)[ITC], int c, int it0) {
       const char* cbase = (const char*)spec + (size_t)c * cstride;
 #pragma unroll
       for (int k = 0; k < ITC; ++k) {
         const int it = it0 + k;
-        const int i = tid + it * 256;
+        const int i = tid + it * NTX;
         if (i < 2 * N * TY) v[k] = ldo<T>(cbase, off0 + (uint32_t)it * OFF_IT * (uint32_t)a.nz);
       }
     };
@@ -377,7 +394,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
         load(acc, 0, it0);
         if (it0 == 0) {
           __syncthreads();  // tw visible
-          fill_twl_any<T, N>(twl, tw, tid, 256);
+          fill_twl_any<T, N>(twl, tw, tid, NTX);
         }
       } else {
         cplx<T> va[ITC], vb[ITC];
@@ -385,7 +402,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
         load(vb, CL - 2, it0);
         if (it0 == 0) {
           __syncthreads();  // tw visible
-          fill_twl_any<T, N>(twl, tw, tid, 256);
+          fill_twl_any<T, N>(twl, tw, tid, NTX);
         }
         const cplx<T> wy = conj(tw[y0 + tid % TY]);
 #pragma unroll
@@ -404,7 +421,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
       }
 #pragma unroll
       for (int k = 0; k < ITC; ++k) {
-        const int i = tid + (it0 + k) * 256;
+        const int i = tid + (it0 + k) * NTX;
         if (i < 2 * N * TY) {
           const int yy = i % TY;
           const int kx = i / TY;
@@ -427,7 +444,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   cplx<T> q0[IT], q1[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    const int i = tid + it * 256;
+    const int i = tid + it * NTX;
     if (i < TY * N) {
       const size_t idx = row0 + i;
       if constexpr (EPI == EPI_AXV) {
@@ -448,7 +465,7 @@ __global__ __launch_bounds__(256) void k_xinv(PassArgs a) {
   cplx<double> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    const int i = tid + it * 256;
+    const int i = tid + it * NTX;
     if (i < TY * N) {
       const int yy = i / N;
       const int x = i - yy * N;
@@ -1430,17 +1447,17 @@ static hipError_t xinv_t(const PassArgs& a, hipStream_t s) {
   constexpr int CL = ClassCfg<T, N>::C;
   if (a.spec2 < 0) {  // plain spectrum (far-field transpose)
     if (a.mode != EPI_STORE) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, 1>), nb, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, 1>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a);
     return hipGetLastError();
   }
   switch (a.mode) {
-    case EPI_STORE: hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, CL>), nb, dim3(256), 0, s, a); break;
-    case EPI_AXV: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXV, CL>), nb, dim3(256), 0, s, a); break;
-    case EPI_AXT: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXT, CL>), nb, dim3(256), 0, s, a); break;
-    case EPI_R0: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0, CL>), nb, dim3(256), 0, s, a); break;
-    case EPI_TRUE: hipLaunchKernelGGL((k_xinv<T, N, EPI_TRUE, CL>), nb, dim3(256), 0, s, a); break;
-    case EPI_R0X: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0X, CL>), nb, dim3(256), 0, s, a); break;
-    case EPI_AX: hipLaunchKernelGGL((k_xinv<T, N, EPI_AX, CL>), nb, dim3(256), 0, s, a); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
+    case EPI_AXV: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXV, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
+    case EPI_AXT: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXT, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
+    case EPI_R0: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
+    case EPI_TRUE: hipLaunchKernelGGL((k_xinv<T, N, EPI_TRUE, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
+    case EPI_R0X: hipLaunchKernelGGL((k_xinv<T, N, EPI_R0X, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
+    case EPI_AX: hipLaunchKernelGGL((k_xinv<T, N, EPI_AX, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
