@@ -78,3 +78,25 @@ def test_maxit_reports_nonconvergence():
     b = incident.plane_wave(n, K, [0, 0, 1])
     x, info = solver.bicgstab(lambda v: ops.A_apply(gh, f, v), b, 1e-14, maxit=2, max_restarts=0)
     assert info.status == 1 and info.iters == 2
+
+
+def test_bicgstab_initial_guess():
+    # any starting point converges to the dense LU solution; starting at that solution the
+    # initial residual test accepts it with no iteration; a start closer to the solution needs
+    # no more iterations than the incident field
+    n, p = 6, 4
+    gm = kernel.gm_coset(n, p, K)
+    gh = np.fft.fftn(gm)
+    f = workloads.sphere_potential(n, 2.0, 1.8)
+    b = incident.plane_wave(n, K, [0, 0.6, 0.8])
+    A = lambda v: ops.A_apply(gh, f, v)  # noqa: E731
+    ref = solver.dense_solve(ops.G_dense(gm, n), f, b)
+    rng = np.random.default_rng(3)
+    x0 = rng.standard_normal(b.shape) + 1j * rng.standard_normal(b.shape)
+    x, info = solver.bicgstab(A, b, 1e-13, x0=x0)
+    assert info.status == 0 and np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-11
+    x, info = solver.bicgstab(A, b, 1e-10, x0=ref)
+    assert info.status == 0 and info.iters == 0 and info.matvecs == 1 and np.array_equal(x, ref)
+    _, cold = solver.bicgstab(A, b, 1e-10)
+    _, warm = solver.bicgstab(A, b, 1e-10, x0=ref + 1e-6 * (x0 - ref))
+    assert warm.iters <= cold.iters
