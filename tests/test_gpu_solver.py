@@ -235,3 +235,25 @@ def test_warm_start_follows_the_oracle_from_the_same_initial_guess():
     u32, i32 = c64.ls_forward(torch.from_numpy(f.astype(np.float32)).to(DEV), d, tol=1e-5, u=u32, warm_start=True)
     assert i32[0]["status"] == 0 and i32[0]["iters"] == 0 and i32[0]["relres_true"] < 1e-5
     assert rel(u32[0].cpu().numpy(), ut) < 1e-6
+
+
+def test_warm_start_at_128_c64():
+    # the class-split x-inverse (four ky classes at 128^3) with the warm-start initial residual:
+    # restarting from a loose solution reaches the cold solution to the solver tolerance with
+    # fewer iterations, and restarting from a converged solution is accepted at once
+    n, Q = 128, 4
+    c = ctx(n, "c64")
+    f = torch.from_numpy(workloads.blob_potential(0, n, dn_max=0.05).astype(np.float32)).to(DEV)
+    d = workloads.cone_dirs(Q, 45.0)
+    ucold, icold = c.ls_forward(f, d, tol=1e-5)
+    uloose, _ = c.ls_forward(f, d, tol=1e-2)
+    uwarm, iwarm = c.ls_forward(f, d, tol=1e-5, u=uloose.clone(), warm_start=True)
+    e = max(rel(uwarm[q].cpu().numpy(), ucold[q].cpu().numpy()) for q in range(Q))
+    print(f"[warm 128] iterations cold {[i['iters'] for i in icold]}, from tol 1e-2 {[i['iters'] for i in iwarm]}; "
+          f"max difference {e:.2e}", flush=True)
+    assert all(i["status"] == 0 and i["relres_true"] <= 1e-5 for i in iwarm)
+    assert sum(i["iters"] for i in iwarm) < sum(i["iters"] for i in icold)
+    # two solutions with relative residual <= 1e-5 each; the operator is well conditioned here
+    assert e < 1e-4
+    _, iagain = c.ls_forward(f, d, tol=1e-5, u=uwarm.clone(), warm_start=True)
+    assert all(i["status"] == 0 and i["iters"] == 0 for i in iagain)
