@@ -11,7 +11,9 @@ does not spell them out):
   * after the loop, the true residual b - A x is recomputed; if it exceeds tol and restarts
     remain, the iteration restarts from x.
 The same recurrence runs on the GPU with FP64 scalars.  Pinned against a dense LU solve on
-tiny grids (tests/test_oracle_solver.py).
+tiny grids; the restart branches by a breakdown threshold that fires, one that fires at every step
+(the plain two-stage descent), and a true-residual restart equal to a fresh solve from the restart
+point (tests/test_oracle_solver.py).
 """
 from __future__ import annotations
 

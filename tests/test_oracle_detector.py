@@ -3,7 +3,10 @@
 Wide far field: equals the brute-force double sum for m > n; equals the already pinned square
 detector (oracle.farfield) when m = n; its central n x n pixels equal the square detector's for any
 m (same positions, same sum); its transpose satisfies the bilinear identity.  Pupil: identity when
-the pupil covers the whole grid and dz = 0; adjoint identity; never increases energy.  Decimation:
+the pupil covers the whole grid and dz = 0; adjoint identity; never increases energy; its impulse
+response at dz = 0 is the Airy pattern of a disk of radius na k (pins the cutoff); it carries the
+field of a beamed source from x_Gamma to x_Gamma + dz as the far-field sum at the farther plane gives
+it (pins the sign and wavenumber of the propagation phase).  Decimation:
 keeps the pixel at the lateral origin; adjoint identity.
 """
 import numpy as np
@@ -98,3 +101,50 @@ def test_chain_gradient_central_differences():
         e = e.reshape(f0.shape)
         fd = (loss(f0 + e) - loss(f0 - e)) / (2 * eps)
         assert abs(fd - g.ravel()[idx]) <= 1e-6 * np.abs(g).max(), (idx, fd, g.ravel()[idx])
+
+
+def test_pupil_impulse_response_is_the_airy_pattern():
+    # at dz = 0 the pupil is the ideal low-pass of radius W = na k: the response to one pixel is the
+    # inverse transform of a disk, W J1(W r) / (2 pi r) (W^2 / (4 pi) at r = 0) up to the sampling of
+    # the disk on the 2m frequency grid, which shrinks as m grows.  A cutoff at na k0 (the vacuum
+    # wavenumber) would scale the central value by 1 / 1.333^2.
+    from scipy import special
+    k = workloads.k_of()
+    for na in (0.5, 1.0):
+        W = na * k
+        errs = []
+        for m in (64, 128):
+            y = np.zeros((m, m), dtype=np.complex128)
+            a0 = m // 2 - 1
+            y[a0, a0] = 1.0
+            out = det.pupil(y, k, na, 0.0)
+            pos = np.arange(m) - a0
+            R = np.sqrt(pos[:, None] ** 2 + pos[None, :] ** 2)
+            airy = W * W / (4 * np.pi) * np.ones_like(R)
+            nz = R > 0
+            airy[nz] = W * special.j1(W * R[nz]) / (2 * np.pi * R[nz])
+            sel = R <= 12
+            errs.append(np.max(np.abs(out[sel] - airy[sel])) / airy.max())
+        assert errs[1] < errs[0] < 1e-2 and errs[1] < 3e-3, (na, errs)
+
+
+def test_pupil_propagates_the_field_to_the_next_plane():
+    # a field that solves the homogeneous Helmholtz equation beyond the detector plane is carried
+    # from x3 = x_Gamma to x3 = x_Gamma + dz by multiplying its angular spectrum with
+    # exp(+i dz sqrt(k^2 - |w|^2)).  The far field of a source beamed along the axis (a Gaussian
+    # envelope times exp(i k x3), little energy near the cutoff |w| = k) computed at x_Gamma and sent
+    # through the pupil (na = 1) must therefore match the far field computed directly at
+    # x_Gamma + dz, on the central half of a wide detector (finite window).  The opposite sign, or
+    # the vacuum wavenumber in the cutoff, gives errors of order 1 or 1e-1.
+    k = workloads.k_of()
+    n, m, sig, xg, dz = 16, 64, 3.0, 10.0, 4.0
+    c = np.arange(n) - n // 2 + 1.0
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    for th in (0.0, 0.3):
+        v = np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / (2 * sig ** 2)) * np.exp(1j * k * (np.sin(th) * X + np.cos(th) * Z))
+        y1 = det.farfield_wide_fft(v, k, xg, m)
+        y2 = det.farfield_wide_fft(v, k, xg + dz, m)
+        yp = det.pupil(y1, k, 1.0, dz)
+        cc = slice(m // 4, 3 * m // 4)
+        e = np.linalg.norm((yp - y2)[cc, cc]) / np.linalg.norm(y2[cc, cc])
+        assert e < 2e-3, (th, e)

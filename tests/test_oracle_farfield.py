@@ -41,3 +41,28 @@ def test_single_voxel_source_is_green_function():
     dx = c[None, :] - c[1]
     ref = green.g_free(np.sqrt(dy ** 2 + dx ** 2 + Z ** 2), K)
     assert np.max(np.abs(y - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_far_field_of_a_radial_source_is_the_outgoing_wave():
+    # outside a radially symmetric source v(rho) (support rho < a) the convolution with
+    # g = exp(ikr)/(4 pi r) is the outgoing spherical wave (exp(ikr)/(kr)) int_0^a v rho sin(k rho) drho
+    # (the mean of g over a sphere of radius rho about the origin is g(r) sin(k rho)/(k rho) for
+    # r > rho).  The detector operator is the rectangle rule of that convolution on the voxel grid,
+    # so h^2 G~ v at the detector pixels must approach it as the grid is refined (a smooth bump:
+    # fast convergence).  Physical units: cube side L = 8, detector plane x3 = L, i.e. x_Gamma = n
+    # voxels; the voxel-unit operator carries k h, and h^3 sum g(h .) = h^2 sum g~(.).
+    from scipy import integrate
+    from oracle import bump
+    L, kb, a, q = 8.0, 1.3, 2.8, 4
+    moment = integrate.quad(lambda r: bump.bump(r, a, q) * r * np.sin(kb * r), 0.0, a, epsabs=1e-15, epsrel=1e-13)[0]
+    errs = []
+    for n in (8, 16, 32):
+        h = L / n
+        c = (np.arange(n) - n // 2 + 1) * h
+        Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+        v = bump.bump(np.sqrt(X ** 2 + Y ** 2 + Z ** 2), a, q).astype(np.complex128)
+        y = h * h * farfield.farfield_fft(v, kb * h, float(n))
+        r = np.sqrt(c[:, None] ** 2 + c[None, :] ** 2 + L * L)
+        ref = np.exp(1j * kb * r) / (kb * r) * moment
+        errs.append(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    assert errs[0] > 30 * errs[1] > 900 * errs[2] and errs[2] < 1e-6, errs

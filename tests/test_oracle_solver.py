@@ -1,5 +1,9 @@
 """Pins for oracle.solver and oracle.incident: BiCGSTAB against a dense LU solve, the f = 0 and
-Born limits, discrete reciprocity, and plane-wave structure."""
+Born limits, discrete reciprocity, and plane-wave structure.  The restart branches: a breakdown
+threshold that fires (still converging to the LU solution), a threshold that fires at every step
+(the iteration becomes the plain two-stage descent written out in the test), and a true-residual
+restart forced by an operator whose first application is off (equal to a fresh solve from the
+restart point, bit for bit)."""
 import numpy as np
 import pytest
 
@@ -100,3 +104,92 @@ def test_bicgstab_initial_guess():
     _, cold = solver.bicgstab(A, b, 1e-10)
     _, warm = solver.bicgstab(A, b, 1e-10, x0=ref + 1e-6 * (x0 - ref))
     assert warm.iters <= cold.iters
+
+
+def _sphere_problem(n=6, radius=2.5, eta=1.8):
+    gm = kernel.gm_coset(n, 4, K)
+    gh = np.fft.fftn(gm)
+    f = workloads.sphere_potential(n, radius, eta)
+    b = incident.plane_wave(n, K, [0, 0, 1])
+    ref = solver.dense_solve(ops.G_dense(gm, n), f, b)
+    return (lambda v: ops.A_apply(gh, f, v)), b, ref
+
+
+def test_breakdown_restart_converges_to_dense_lu():
+    # a breakdown threshold of 1/2 makes the restart (r^ = r, p = v = 0, rho_prev = alpha = omega = 1)
+    # fire whenever r has turned more than 60 degrees away from the shadow residual; the solve still
+    # reaches the dense LU solution
+    A, b, ref = _sphere_problem()
+    x, info = solver.bicgstab(A, b, 1e-13, eps=0.5)
+    assert info.status == 0 and info.restarts >= 3, info
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-11
+
+
+def test_restart_every_iteration_is_the_two_stage_descent():
+    # with a threshold above every attainable |cos(r^, r)| each iteration after the first restarts,
+    # so every step uses p = r and r^ = r: a Galerkin step along r (alpha = ||r||^2 / <r, A r>)
+    # followed by a minimal-residual step along s (omega = <A s, s> / ||A s||^2).  Written out
+    # here as that plain two-stage descent, it must give the same iterates, and the same solution.
+    A, b, ref = _sphere_problem()
+    tol = 1e-12
+    x, info = solver.bicgstab(A, b, tol, eps=0.999999)
+    assert info.status == 0 and info.restarts == info.iters - 1, info
+    nb = np.linalg.norm(b)
+    y = b.copy()
+    r = b - A(y)
+    hist = []
+    for _ in range(10_000):
+        Ar = A(r)
+        al = np.vdot(r, r) / np.vdot(r, Ar)
+        s = r - al * Ar
+        if np.linalg.norm(s) / nb <= tol:
+            y = y + al * r
+            hist.append(np.linalg.norm(s) / nb)
+            break
+        As = A(s)
+        om = np.vdot(As, s) / np.vdot(As, As)
+        y = y + al * r + om * s
+        r = s - om * As
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= tol:
+            break
+    assert len(hist) == info.iters
+    assert np.allclose(hist, info.history, rtol=1e-6, atol=0)
+    assert np.linalg.norm(x - y) / np.linalg.norm(y) < 1e-11
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_true_residual_restart_equals_a_fresh_solve_from_that_point():
+    # an operator whose first application (the initial residual) is off by 1e-3 makes the recursion
+    # converge to the solution of a shifted system; the recomputed true residual b - A x is then
+    # ~1e-3 > tol, so the solver restarts from x with r = r^ = b - A x.  That restart must be the
+    # same computation as a new solve started at x, and it must end at the dense LU solution.
+    A, b, ref = _sphere_problem()
+    tol = 1e-12
+
+    def off_once():
+        calls = [0]
+
+        def op(v):
+            calls[0] += 1
+            return A(v) * (1.0 + 1e-3) if calls[0] == 1 else A(v)
+        return op
+
+    x, info = solver.bicgstab(off_once(), b, tol, max_restarts=3)
+    assert info.status == 0 and info.restarts == 1, info
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
+    # the same start without restarts stops at the restart point with the failed check
+    x1, info1 = solver.bicgstab(off_once(), b, tol, max_restarts=0)
+    assert info1.status == 2 and info1.relres_true > 1e-5 and info1.relres_rec <= tol
+    x2, info2 = solver.bicgstab(A, b, tol, x0=x1)
+    assert np.array_equal(x, x2)
+    assert info.iters == info1.iters + info2.iters
+    assert info.matvecs == info1.matvecs + info2.matvecs - 1   # the fresh solve's r0 is the check
+
+
+def test_zero_right_hand_side_returns_zero_from_any_start():
+    # A x = 0 has the solution x = 0 whatever the initial guess
+    A, b, _ = _sphere_problem()
+    x0 = workloads.random_field(4, b.shape)
+    x, info = solver.bicgstab(A, np.zeros_like(b), 1e-10, x0=x0)
+    assert info.status == 0 and info.iters == 0 and not np.any(x)
