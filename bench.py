@@ -1,17 +1,21 @@
 #!/usr/bin/env python
 """Benchmark of the hot path: LS solves/s on the 128^3 x 60-illumination workload.
 
-One step = ls_forward (BiCGSTAB to tol 1e-5 for all 60 plane waves on a 45-degree cone, blob
-phantom seed 0, complex64 fields with FP64 reductions) + ls_farfield (128 x 128 detector per
-illumination).  Inputs are resident in HBM before the timed region; the one-time Green-kernel
-build is timed separately.  Prints one JSON line.
+One step = ls_forward_farfield: BiCGSTAB to tol 1e-5 for all 60 plane waves on a 45-degree cone
+(blob phantom seed 0, complex64 fields with FP64 reductions) and the far field of every solution
+(128 x 128 detector per illumination).  Inputs are resident in HBM before the timed region; the one-time Green-kernel
+build is timed separately.  Prints one JSON line whose headline is that workload; the same line
+carries the 256^3 x 60 forward workload and the 128^3 x 40-view gradient workload as
+sub-objects (`configs`), the accuracy of the timed batch against the complex128 path, and the
+FP64 oracle timed on the host (`cpu_baseline`).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload B] [--no-extras] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -22,6 +26,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK = 78.6   # TFLOP/s: 256 CU x 64 FMA lanes/clk x 2 x 2.4 GHz, non-packed FP32
 FP32_PACKED_PEAK = 157.3  # TFLOP/s with packed (2-wide) FP32 FMA; the kernels are compiled without packed FP32
+ACC_QS = (0, 15, 30, 45)  # illuminations compared with the complex128 path
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def pct(a, q):
@@ -29,13 +38,210 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+def rel(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def classes(n, c128):
+    """ky classes of the (y,z) plane pass (ClassCfg in kernels.hip)."""
+    return {True: {8: 2, 16: 2, 32: 2, 64: 2, 96: 6, 128: 8, 144: 18, 192: 12, 256: 16},
+            False: {8: 2, 16: 2, 32: 2, 64: 2, 96: 2, 128: 4, 144: 6, 192: 6, 256: 8}}[c128][n]
+
+
+def pass_model(n, Q, c128):
+    """Algorithmic bytes (and the plane pass's flops) per launch of the four solver passes.
+
+    Bytes in units of N*c per slot:
+      k_xfwd (p-update prologue): read r p v (3) + f (0.5), write p (1) + x-spectrum (2) = 6.5
+      k_yz   read the x-spectrum (2), write the class-split (y,z) output (4) = 6, + kernel once
+      k_xinv (v epilogue): read the class output (4) + p, rh (2), write v (1) = 7
+      k_update: read x p s t rh (5), write x r (2) = 7
+    Plane-pass flops with C ky classes of M = 2n/C points (5 L log2 L per L-point transform): per
+    (slot, kx) C x [n forward + n inverse M-point row DFTs + M columns x 4 n-point DFTs
+    (z-convolution)] + 6 flops per kernel product."""
+    c = 16 if c128 else 8
+    Nc = n ** 3 * c
+    ker_bytes = (n + 1) * 4 * n * n * c
+    C = classes(n, c128)
+    Mc = 2 * n // C
+    yz_flops = Q * 2 * n * C * (2 * n * 5 * Mc * math.log2(Mc) + Mc * 4 * 5 * n * math.log2(n) + 2 * Mc * n * 6)
+    return {"k_xfwd": (0, Q * 6.5 * Nc, 2), "k_yz": (1, Q * 6 * Nc + ker_bytes, 2),
+            "k_xinv": (2, Q * 7 * Nc, 2), "k_update": (3, Q * 7 * Nc, 1)}, yz_flops
+
+
+def time_passes(ctx, f, u, ws, n, Q, c128, reps):
+    """Average launch time of each solver pass, HIP events on the stream the passes run on."""
+    import torch
+
+    from paper_1910_13844_amd import api
+    model, yz_flops = pass_model(n, Q, c128)
+    stream = torch.cuda.current_stream()
+    kern = {}
+    for name, (pid, nbytes, per_it) in model.items():
+        api.profile_pass(ctx, f, u, pid, 1, ws)  # warm
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        api.profile_pass(ctx, f, u, pid, reps, ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        kern[name] = {"avg_ms": ms, "alg_bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9, "share": per_it * ms}
+    return kern, yz_flops
+
+
+def timed_steps(step, steps, warmup, tag):
+    import torch
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        step()
+        log(f"{tag} warmup {i} done")
+    torch.cuda.synchronize()
+    times, infos, out = [], [], None
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        info, out = step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        infos.append(info)
+        log(f"{tag} step {k}: {times[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, times, infos, out
+
+
+def forward_workload(W, steps, warmup, dev="cuda:0"):
+    """ls_forward_farfield over the whole batch of workload W; returns timings, the last step's
+    fields and the context (the caller frees them)."""
+    import torch
+
+    from paper_1910_13844_amd import _lib, api
+    n, Q = W.n, W.Q
+    rd = torch.float32 if W.precision == "c64" else torch.float64
+    cd = torch.complex64 if W.precision == "c64" else torch.complex128
+    f = torch.from_numpy(W.potential()).to(dev, rd)
+    t = time.perf_counter()
+    ctx = api.Context(n, W.k, p=W.p, xg=W.xg, prec=W.precision, device=dev)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t
+    log(f"green init n={n}: {t_init * 1e3:.1f} ms")
+    dirs = W.dirs()
+    wsF = ctx.workspace(Q, _lib.LS_OP_FORWARD)
+    u = torch.empty((Q, n, n, n), dtype=cd, device=dev)
+    y = torch.empty((Q, n, n), dtype=cd, device=dev)
+
+    def step():
+        _, _, info = ctx.ls_forward_farfield(f, dirs, tol=W.tol, u=u, y=y, ws=wsF)
+        return info, y
+
+    total, times, infos, y = timed_steps(step, steps, warmup, W.name)
+    last = infos[-1]
+    assert all(i["status"] == 0 for i in last), "not all illuminations converged"
+    return {"ctx": ctx, "f": f, "u": u, "y": y, "wsF": wsF, "t_init": t_init, "total": total, "times": times,
+            "infos": infos, "dirs": dirs}
+
+
+def solve_summary(infos):
+    import numpy as np
+    last = infos[-1]
+    iters = [i["iters"] for i in last]
+    return {"solves_per_step": len(last), "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
+            "matvecs_mean": float(np.mean([i["matvecs"] for i in last])),
+            "restarts": int(sum(i["restarts"] for i in last)),
+            "relres_true_max": float(max(i["relres_true"] for i in last))}
+
+
+def accuracy_vs_c128(W, r, dev="cuda:0"):
+    """Relative L2 error of the timed batch's fields (illuminations ACC_QS) against the complex128
+    path solved to 1e-10 (whose agreement with the FP64 oracle is a parity test)."""
+    import torch
+
+    from paper_1910_13844_amd import api
+    ctx = api.Context(W.n, W.k, p=W.p, xg=W.xg, prec="c128", device=dev)
+    f64 = torch.from_numpy(W.potential()).to(dev)
+    d = r["dirs"][list(ACC_QS)]
+    u64, info = ctx.ls_forward(f64, d, tol=1e-10)
+    y64 = ctx.ls_farfield(f64, u64)
+    eu = [rel(r["u"][q].cpu().numpy().astype("complex128"), u64[i].cpu().numpy()) for i, q in enumerate(ACC_QS)]
+    ey = [rel(r["y"][q].cpu().numpy().astype("complex128"), y64[i].cpu().numpy()) for i, q in enumerate(ACC_QS)]
+    del ctx, u64, y64
+    return {"reference": "complex128 path, tol 1e-10", "illuminations": list(ACC_QS),
+            "u_rel_l2_max": max(eu), "y_rel_l2_max": max(ey), "u_rel_l2": eu, "y_rel_l2": ey,
+            "ref_iters": [i["iters"] for i in info]}
+
+
+def release(d=None):
+    """Drops the device buffers held in dict d (if given) and returns cached blocks to the device."""
+    import gc
+
+    import torch
+    if d is not None:
+        d.clear()
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def config_C(steps, warmup, reps):
+    from paper_1910_13844_amd import workloads
+    W = workloads.WORKLOADS["C"]
+    r = forward_workload(W, steps, warmup)
+    kern, _ = time_passes(r["ctx"], r["f"], r["u"].clone(), r["wsF"], W.n, W.Q, False, reps)
+    s = solve_summary(r["infos"])
+    out = {"workload": W.name, "n": W.n, "padded_fft": 2 * W.n, "illuminations": W.Q, "tol": W.tol,
+           "value": round(W.Q * steps / r["total"], 3), "unit": "solves/s",
+           "ms_per_step": round(1e3 * r["total"] / steps, 2), "steps": steps, "warmup": warmup,
+           "iters_per_solve": s["iters_mean"], "solve": s, "green_init_ms": round(r["t_init"] * 1e3, 1),
+           "passes": {k: {"avg_ms": round(v["avg_ms"], 4), "GB/s": round(v["gbs"], 1),
+                          "hbm_frac": round(v["gbs"] / HBM_PEAK_GBS, 4)} for k, v in kern.items()}}
+    release(r)
+    return out
+
+
+def config_D(steps, warmup, dev="cuda:0"):
+    import numpy as np
+    import torch
+
+    from paper_1910_13844_amd import _lib, api, workloads
+    W = workloads.WORKLOADS["D"]
+    n, Q = W.n, W.Q
+    ctx = api.Context(n, W.k, p=W.p, xg=W.xg, prec=W.precision, device=dev)
+    f0, f_true = workloads.perturbed_potential(n, W.seed)
+    f = torch.from_numpy(f0).to(dev, torch.float32)
+    ft = torch.from_numpy(f_true).to(dev, torch.float32)
+    dirs = W.dirs()
+    u, _ = ctx.ls_forward(ft, dirs, tol=W.tol)
+    yhat = torch.from_numpy(workloads.add_noise(ctx.ls_farfield(ft, u).cpu().numpy())).to(dev, torch.complex64)
+    del u, ft
+    wsG = ctx.workspace(Q, _lib.LS_OP_GRAD)
+
+    def step():
+        loss, g, info = ctx.ls_grad(f, dirs, yhat, tol=W.tol, ws=wsG)
+        return info, (loss, g)
+
+    total, times, infos, (loss, g) = timed_steps(step, steps, warmup, W.name)
+    info = infos[-1]
+    assert all(i["status"] == 0 for i in info)
+    it = [i["iters"] for i in info]
+    out = {"workload": W.name, "n": n, "views": Q, "tol": W.tol, "value": round(steps / total, 3),
+           "unit": "gradients/s", "ms_per_step": round(1e3 * total / steps, 2), "steps": steps, "warmup": warmup,
+           "solves_per_gradient": len(info), "iters_mean": float(np.mean(it)), "loss": loss,
+           "accuracy": "gradient vs the FP64 oracle solved to 1e-11 (n = 32, same construction): "
+                       "tests/test_gpu_workloads.py bar 1e-4"}
+    del ctx, wsG, f, yhat, g
+    release()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="B")
+    ap.add_argument("--workload", default="B", choices=["A", "B", "C"])
     ap.add_argument("--prof-reps", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only (no configs, no accuracy)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (reference for rocprofv3 byte counters)")
@@ -48,112 +254,20 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1910_13844_amd import _lib, api, workloads
+    from paper_1910_13844_amd import workloads
 
     W = workloads.WORKLOADS[args.workload]
     n, Q = W.n, W.Q
-    dev = "cuda:0"
-    f_np = W.potential()
-    dirs = W.dirs()
-    rd = torch.float32 if W.precision == "c64" else torch.float64
-    cd = torch.complex64 if W.precision == "c64" else torch.complex128
-    f = torch.from_numpy(f_np).to(dev, rd)
-
-    t = time.perf_counter()
-    ctx = api.Context(n, W.k, p=W.p, xg=W.xg, prec=W.precision, device=dev)
-    torch.cuda.synchronize()
-    t_init = time.perf_counter() - t
-    print(f"[bench] green init n={n}: {t_init * 1e3:.1f} ms", file=sys.stderr, flush=True)
-
-    wsF = ctx.workspace(Q, _lib.LS_OP_FORWARD)
-    wsFF = ctx.workspace(Q, _lib.LS_OP_FARFIELD)
-    u = torch.empty((Q, n, n, n), dtype=cd, device=dev)
-    stream = torch.cuda.current_stream()
-    grad_mode = W.kind == "gradient"
-
-    if grad_mode:
-        # measured data: fields of the perturbed potential with 30 dB noise (untimed)
-        _, f_true = workloads.perturbed_potential(n, W.seed)
-        ft = torch.from_numpy(f_true).to(dev, rd)
-        ctx.ls_forward(ft, dirs, tol=W.tol, u=u, ws=wsF)
-        yhat = torch.from_numpy(workloads.add_noise(ctx.ls_farfield(ft, u, ws=wsFF).cpu().numpy())).to(dev, cd)
-        del ft
-        wsG = ctx.workspace(Q, _lib.LS_OP_GRAD)
-
-        def step():
-            loss, g, info = ctx.ls_grad(f, dirs, yhat, tol=W.tol, ws=wsG)
-            return info, g
-    else:
-        def step():
-            _, info = ctx.ls_forward(f, dirs, tol=W.tol, u=u, ws=wsF)
-            y = ctx.ls_farfield(f, u, ws=wsFF)
-            return info, y
-
-    for i in range(args.warmup):
-        step()
-        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    times, infos = [], []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        info, y = step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-        infos.append(info)
-        print(f"[bench] step {k}: {times[-1]:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    value = (1 if grad_mode else Q) * args.steps / total
-    last = infos[-1]
-    iters = [i["iters"] for i in last]
-    mvs = [i["matvecs"] for i in last]
-    relres = [i["relres_true"] for i in last]
-    assert all(i["status"] == 0 for i in last), "not all illuminations converged"
+    c128 = W.precision == "c128"
+    r = forward_workload(W, args.steps, args.warmup)
+    value = Q * args.steps / r["total"]
+    s = solve_summary(r["infos"])
 
     # ---- per-kernel live timing of the four solver passes (HIP events on the launch stream)
-    c = 16 if W.precision == "c128" else 8
-    N = n ** 3
-    Nc = N * c
-    ker_bytes = (n + 1) * 4 * n * n * c
-    passes = {
-        "k_xfwd": (0, Q * 6.5 * Nc, 2),
-        "k_yz": (1, Q * 6 * Nc + ker_bytes, 2),
-        "k_xinv": (2, Q * 7 * Nc, 2),
-        "k_update": (3, Q * 7 * Nc, 1),
-    }
-    # algorithmic bytes per launch (units of N*c per slot):
-    #   k_xfwd (p-update prologue): read r p v (3) + f (0.5), write p (1) + x-spectrum (2)
-    #   k_yz   read the x-spectrum (2), write the class-split (y,z) output (4), + kernel once
-    #   k_xinv (v epilogue): read the class output (4) + p, rh (2), write v (1)
-    #   k_update: read x p s t rh (5), write x r (2)
-    # FFT flops of the (y,z) pass with C ky classes of M = 2n/C points (5 L log2 L per L-point
-    # transform): per (slot, kx) C x [n forward + n inverse M-point row DFTs + M columns x 4
-    # n-point DFTs (z-convolution)] + pointwise kernel products
-    import math
-    C = {True: {8: 2, 16: 2, 32: 2, 64: 2, 96: 6, 128: 8, 144: 18, 192: 12, 256: 16},
-         False: {8: 2, 16: 2, 32: 2, 64: 2, 96: 2, 128: 4, 144: 6, 192: 6, 256: 8}}[W.precision == "c128"][n]
-    Mc = 2 * n // C
-    yz_flops = Q * 2 * n * C * (2 * n * 5 * Mc * math.log2(Mc) + Mc * 4 * 5 * n * math.log2(n)
-                                + 2 * Mc * n * 6)
-    prof_ws = torch.empty_like(wsF)
-    prof_u = u.clone()
-    kern = {}
-    for name, (pid, nbytes, per_it) in passes.items():
-        api.profile_pass(ctx, f, prof_u, pid, 1, prof_ws)  # warm
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        api.profile_pass(ctx, f, prof_u, pid, args.prof_reps, prof_ws)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.prof_reps
-        kern[name] = {"avg_ms": ms, "alg_bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9,
-                      "share": per_it * ms}
-    del prof_ws, prof_u
+    kern, yz_flops = time_passes(r["ctx"], r["f"], r["u"].clone(), torch.empty_like(r["wsF"]), n, Q, c128,
+                                 args.prof_reps)
     if args.calib_copy:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
@@ -179,44 +293,45 @@ def main() -> int:
 
     if args.workload == "B":
         metric = "LS solves/sec at 128^3x60 illum, FP32 vs plain at 1e-4 rel err; p50/p99 ms"
-    elif grad_mode:
-        metric = f"data-term gradients/sec at {n}^3x{Q} views ({W.precision}, tol {W.tol:g}); p50/p99 ms"
     else:
         metric = f"LS solves/sec at {n}^3x{Q} illum ({W.precision}, tol {W.tol:g}); p50/p99 ms"
-    solve_ms = [i["time_ms"] for step_info in infos for i in step_info]
+    solve_ms = [i["time_ms"] for step_info in r["infos"] for i in step_info]
     assert min(solve_ms) > 0, "every solve reports its device completion time"
     out = {
         "metric": metric,
         "value": round(value, 3),
-        "unit": "gradients/s" if grad_mode else "solves/s",
+        "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * total / args.steps, 2),
+        "ms_per_step": round(1e3 * r["total"] / args.steps, 2),
         # per-solve completion time over all timed steps: device clock from the batch's first pass
         # to the step at which that illumination's solve reached its final state
         "p50_ms": round(pct(solve_ms, 50), 2),
         "p99_ms": round(pct(solve_ms, 99), 2),
-        "step_p50_ms": round(pct(times, 50), 2),
-        "step_p99_ms": round(pct(times, 99), 2),
+        "step_p50_ms": round(pct(r["times"], 50), 2),
+        "step_p99_ms": round(pct(r["times"], 99), 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 fields, f64 reductions" if W.precision == "c64" else "c128",
+        "dtype": "c128" if c128 else "c64 fields, f64 reductions",
         "data": data_description(W),
         "config": {"workload": W.name, "n": n, "padded_fft": 2 * n, "illuminations": Q, "group_size": Q, "tol": W.tol,
-                   "detector": f"{n}x{n}", "p": W.p, "green_init_ms": round(t_init * 1e3, 1)},
-        "solve": {"solves_per_step": len(last), "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
-                  "matvecs_mean": float(np.mean(mvs)), "relres_true_max": float(max(relres))},
+                   "detector": f"{n}x{n}", "p": W.p, "green_init_ms": round(r["t_init"] * 1e3, 1)},
+        "solve": s,
         "roofline": roof,
         "kernels": per_kernel,
     }
-
+    u0 = r["u"][0].cpu().numpy().astype(np.complex128)
+    y0 = r["y"][0].cpu().numpy().astype(np.complex128)
+    if not args.no_extras and args.workload == "B":
+        out["accuracy"] = accuracy_vs_c128(W, r)
+    f_np = W.potential()
+    release(r)
+    if not args.no_extras and args.workload == "B":
+        out["configs"] = {"C": config_C(2, 1, 2), "D": config_D(5, 1)}
     if not args.no_cpu_baseline:
-        if grad_mode:   # fields of f0 for the oracle's residual check (u held the data fields)
-            ctx.ls_forward(f, dirs, tol=W.tol, u=u, ws=wsF)
-        out["cpu_baseline"], out["oracle_check"] = cpu_baseline(W, f_np, dirs, u, float(np.mean(mvs)),
-                                                                per_step=len(last), grad_mode=grad_mode)
+        out["cpu_baseline"], out["oracle_check"] = cpu_baseline(W, f_np, out["solve"], u0, y0)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -263,40 +378,38 @@ def host_description():
     return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
-def cpu_baseline(W, f_np, dirs, u, mv_per_solve, per_step=1, grad_mode=False):
-    """The FP64 oracle timed on the host: one application of A = I - G diag f at the full size
-    (two FFTs of (2n)^3) and one far field, scaled by the matvecs per solve of the GPU run.  The
-    same matvec gives the oracle's residual of the GPU solution for illumination 0."""
+def cpu_baseline(W, f_np, gpu_solve, u0, y0):
+    """The FP64 oracle timed on the host: one whole BiCGSTAB solve of illumination 0 (all its
+    iterations, the workload's tolerance) and its far field, FFTs on all host cores.  Its solution
+    also measures the GPU's: relative L2 of the timed batch's u and y for that illumination."""
     import numpy as np
 
-    from oracle import farfield as ofar
-    from oracle import incident, kernel, ops
+    from oracle import dft, farfield as ofar
+    from oracle import incident, kernel, ops, solver
 
     n = W.n
+    d = W.dirs()[0]
     t = time.perf_counter()
     gh = kernel.ghat_m(n, W.p, W.k)
     t_setup = time.perf_counter() - t
-    u0 = u[0].cpu().numpy().astype(np.complex128)
-    b = incident.plane_wave(n, W.k, dirs[0])
+    log(f"oracle kernel setup {t_setup:.1f} s")
+    b = incident.plane_wave(n, W.k, d)
     t = time.perf_counter()
-    Au = ops.A_apply(gh, f_np, u0)
-    t_mv = time.perf_counter() - t
-    relres = float(np.linalg.norm(b - Au) / np.linalg.norm(b))
+    uo, info = solver.bicgstab(lambda v: ops.A_apply(gh, f_np, v), b, W.tol)
+    t_solve = time.perf_counter() - t
     t = time.perf_counter()
-    ofar.farfield_fft(f_np * u0, W.k, W.xg)
+    yo = ofar.farfield_fft(f_np * uo, W.k, W.xg)
     t_ff = time.perf_counter() - t
-    per_solve = t_mv * mv_per_solve + t_ff
-    if grad_mode:   # one gradient = per_step solves (forward and adjoint of every view)
-        base = {"value": round(1.0 / (per_solve * per_step), 8), "unit": "gradients/s", "cores": 1, "kind": "oracle",
-                "host": host_description(), "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
-                           f"{t_ff:.2f} s, scaled by {mv_per_solve:.1f} matvecs/solve x {per_step} solves/gradient; "
-                           f"kernel setup {t_setup:.1f} s excluded")}
-        return base, {"oracle_relres_q0": relres, "tol": W.tol}
-    base = {"value": round(1.0 / per_solve, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "host": host_description(), "sample": (f"1 FP64 application of A (2 FFTs of {2 * n}^3, numpy) = {t_mv:.2f} s and 1 far field = "
-                       f"{t_ff:.2f} s, scaled by {mv_per_solve:.1f} matvecs/solve; kernel setup {t_setup:.1f} s "
-                       "excluded")}
-    check = {"oracle_relres_q0": relres, "tol": W.tol}
+    log(f"oracle solve {t_solve:.1f} s ({info.iters} iterations), far field {t_ff:.2f} s")
+    base = {"value": round(1.0 / (t_solve + t_ff), 6), "unit": "solves/s", "cores": dft.WORKERS, "kind": "oracle",
+            "host": host_description(),
+            "sample": (f"1 whole FP64 solve of illumination 0 of the batch (tol {W.tol:g}, {info.iters} iterations, "
+                       f"{info.matvecs} operator applications) = {t_solve:.2f} s + its far field {t_ff:.2f} s; "
+                       f"FFTs on {dft.WORKERS} threads (scipy.fft), the rest single-threaded numpy; "
+                       f"one-time kernel setup {t_setup:.1f} s excluded")}
+    check = {"u_rel_l2_q0": rel(u0, uo), "y_rel_l2_q0": rel(y0, yo), "oracle_iters_q0": int(info.iters),
+             "oracle_relres_true_q0": float(info.relres_true), "tol": W.tol,
+             "note": "GPU complex64 vs the oracle, both stopped at the workload tolerance"}
     return base, check
 
 

@@ -59,6 +59,11 @@ typedef struct {
                            field), 1 x0 = the contents of u on entry (warm start, e.g. the fields of
                            the previous reconstruction iterate); other calls use x0 = b */
   int32_t reserved;     /* 0 */
+  double breakdown;     /* breakdown threshold eps of the restart test |<rh, r>| <= eps ||rh|| ||r|| (the
+                           method's safeguard against a vanishing rho; restart with rh = r, p = v = 0).
+                           0 = the unit roundoff of the field precision (default); otherwise 0 < eps < 1.
+                           The test runs from the second iteration on (at the first, rh = r).
+                           LS_ERR_ARG if negative, >= 1 or not finite. */
 } ls_solve_opts;
 
 typedef struct {
@@ -120,6 +125,13 @@ int ls_apply_A(const ls_ctx* ctx, const void* f, const void* v, void* out, int32
 int ls_forward(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, void* u, const ls_solve_opts* opts,
                ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ls_forward followed by the far field of every solution, y_q = G~ (f . u_q) (eq. (lipp2), P = I):
+ * the solve of one illumination and its detector field.  Equal bit for bit to ls_forward then
+ * ls_farfield, without the far field's own x-forward pass: the solver's final true-residual check
+ * already transformed f . u_q.  u: out [Q][N]; y: out [Q][m][m]; ws as for ls_forward. */
+int ls_forward_farfield(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, void* u, void* y,
+                        const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
 /* Far field, eq. (lipp2) with P = I: y_q = G~ (f . u_q) on the detector plane x3 = x_Gamma,
  * a sum over z-slices of 2D aperiodic convolutions with g.  u: [Q][N]; y: out [Q][m][m]. */
 int ls_farfield(const ls_ctx* ctx, const void* f, const void* u, int32_t Q, void* y, void* ws, size_t ws_bytes,
@@ -145,15 +157,18 @@ int ls_grad(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, con
 
 /* Building blocks of the gradient for callers that schedule the solves themselves (the
  * continuous-batching loop):
- *   ls_residual: r_q = y_q - y_meas,q and FP64 sums stats[2q] = ||r_q||^2, stats[2q+1] = ||y_meas,q||^2
- *     (the data term of eq. (prob) is sum_q stats[2q] / (2 stats[2q+1])).  y, y_meas, r: [Q][m][m]
- *     device (r may alias y); stats: [2Q] device doubles.
+ *   ls_residual: FP64 sums stats[2q] = ||y_q - y_meas,q||^2, stats[2q+1] = ||y_meas,q||^2, and
+ *     r_q = y_q - y_meas,q (weighted == 0) or r_q = (y_q - y_meas,q) / ||y_meas,q||^2 (weighted != 0:
+ *     the gradient of the data term with respect to y_q, dL/dRe(y) + i dL/dIm(y)); loss (device double,
+ *     may be NULL) = the data term of eq. (prob), sum_q stats[2q] / (2 stats[2q+1]), summed in q order.
+ *     y, y_meas, r: [Q][m][m] device (r may alias y); stats: [2Q] device doubles.  The weighted form
+ *     needs ||y_meas,q|| > 0.
  *   ls_grad_accumulate: grad[i] (+)= sum_q w_q Re(u_q[i] wb_q[i]) (Algorithm 1, gradient step, with
  *     wb_q solving (I - G diag f) wb_q = G~^T conj(r_q)); w_q = 1 / stats[2q+1] when stats is given,
  *     else 1.  Summed over q in index order in FP64.  u, wb: [Q][N]; grad: [N] real, overwritten when
  *     accumulate == 0, added to otherwise. */
-int ls_residual(const ls_ctx* ctx, const void* y, const void* y_meas, int32_t Q, void* r, double* stats,
-                void* stream);
+int ls_residual(const ls_ctx* ctx, const void* y, const void* y_meas, int32_t Q, int32_t weighted, void* r,
+                double* stats, double* loss, void* stream);
 int ls_grad_accumulate(const ls_ctx* ctx, const void* u, const void* wb, int32_t Q, const double* stats,
                        void* grad, int32_t accumulate, void* stream);
 

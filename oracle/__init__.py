@@ -10,6 +10,7 @@ Everything is plain NumPy/SciPy in complex128/float64, in voxel units (h = 1):
 k = k_b h, L = n, R = sqrt(3) n, delta = 2 pi / (n p), f~ = f h^2.
 
 Modules
+  dft       the DFT and its inverse (scipy.fft over the host cores)
   green     truncated Green function in Fourier, eqs. (GreenL), (GreenL2)
   kernel    Theorem 1 samples and the Proposition 2 modified kernel (two ways)
   ops       the discrete operator G: FFT form, Theorem 1 form, direct sum, dense matrix

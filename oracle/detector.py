@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import green
+from . import dft, green
 
 
 def positions(m: int) -> np.ndarray:
@@ -71,10 +71,10 @@ def wide_kernels(n: int, m: int, k: float, xg: float, M: int) -> np.ndarray:
 def farfield_wide_fft(v: np.ndarray, k: float, xg: float, m: int) -> np.ndarray:
     n = v.shape[0]
     M = fft_size(m, n)
-    Kh = np.fft.fft2(wide_kernels(n, m, k, xg, M))
+    Kh = dft.fft2(wide_kernels(n, m, k, xg, M))
     vp = np.zeros((n, M, M), dtype=np.complex128)
     vp[:, :n, :n] = v
-    y = np.fft.ifft2(np.sum(Kh * np.fft.fft2(vp), axis=0))
+    y = dft.ifft2(np.sum(Kh * dft.fft2(vp), axis=0))
     return y[:m, :m]
 
 
@@ -82,12 +82,12 @@ def farfield_wide_T(r: np.ndarray, k: float, xg: float, n: int) -> np.ndarray:
     """(G~^T r)[z, b] = sum_a g(pos_m(a) - pos_n(b), x_Gamma - z) r[a]  (no conjugation)."""
     m = r.shape[0]
     M = fft_size(m, n)
-    Kh = np.fft.fft2(wide_kernels(n, m, k, xg, M))
+    Kh = dft.fft2(wide_kernels(n, m, k, xg, M))
     rp = np.zeros((M, M), dtype=np.complex128)
     rp[:m, :m] = r
     # transpose of a circular convolution = circular correlation: kernel at negated frequencies
     Kneg = np.roll(Kh[:, ::-1, ::-1], 1, axis=(1, 2))
-    out = np.fft.ifft2(Kneg * np.fft.fft2(rp)[None])
+    out = dft.ifft2(Kneg * dft.fft2(rp)[None])
     return out[:, :n, :n]
 
 
@@ -106,7 +106,7 @@ def pupil(y: np.ndarray, k: float, na: float, dz: float, adjoint: bool = False) 
         p = np.conj(p)
     yp = np.zeros(y.shape[:-2] + (2 * m, 2 * m), dtype=np.complex128)
     yp[..., :m, :m] = y
-    return np.fft.ifft2(p * np.fft.fft2(yp))[..., :m, :m]
+    return dft.ifft2(p * dft.fft2(yp))[..., :m, :m]
 
 
 def decimation_offset(m: int, q: int) -> int:

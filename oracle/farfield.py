@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import green
+from . import dft, green
 
 
 def _signed_n(n):
@@ -75,9 +75,9 @@ def farfield_fft(v: np.ndarray, k: float, xg: float, kern=None) -> np.ndarray:
     M = 2 * n
     if kern is None:
         kern = slice_kernels(n, k, xg)
-    Kh = np.fft.fft2(kern)
-    Vh = np.fft.fft2(_pad2(v, M))
-    Y = np.fft.ifft2(np.sum(Kh * Vh, axis=0))
+    Kh = dft.fft2(kern)
+    Vh = dft.fft2(_pad2(v, M))
+    Y = dft.ifft2(np.sum(Kh * Vh, axis=0))
     return Y[:n, :n]
 
 
@@ -87,10 +87,10 @@ def farfield_T(r: np.ndarray, k: float, xg: float, kern=None) -> np.ndarray:
     M = 2 * n
     if kern is None:
         kern = slice_kernels(n, k, xg)
-    Kh = np.fft.fft2(kern)
-    Rh = np.fft.fft2(_pad2(r, M))
+    Kh = dft.fft2(kern)
+    Rh = dft.fft2(_pad2(r, M))
     # correlation with an even kernel equals convolution
-    out = np.fft.ifft2(Kh * Rh[None])
+    out = dft.ifft2(Kh * Rh[None])
     return out[:, :n, :n]
 
 

@@ -13,6 +13,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import dft
+
 
 def plane_wave(n: int, k: float, d) -> np.ndarray:
     c = np.arange(n, dtype=np.float64) - n // 2 + 1
@@ -58,8 +60,8 @@ def angular_spectrum(y_in: np.ndarray, k: float, xg: float, ktilde=(0.0, 0.0), t
     c = np.arange(n, dtype=np.float64) - n // 2 + 1
     kx, ky = (float(t) for t in ktilde) if tilt_transfer else (0.0, 0.0)
     carrier = np.exp(1j * (kx * c[None, :] + ky * c[:, None]))
-    a_hat = np.fft.fft2(y_in * np.conj(carrier))
+    a_hat = dft.fft2(y_in * np.conj(carrier))
     out = np.empty((n, n, n), dtype=np.complex128)
     for iz in range(n):
-        out[iz] = np.fft.ifft2(a_hat * propagator(n, k, xg - c[iz], (kx, ky))) * carrier
+        out[iz] = dft.ifft2(a_hat * propagator(n, k, xg - c[iz], (kx, ky))) * carrier
     return out

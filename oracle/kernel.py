@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import green
+from . import dft, green
 
 
 def signed(M: int) -> np.ndarray:
@@ -46,7 +46,7 @@ def ghat_grid(n: int, p: int, k: float) -> np.ndarray:
 def gm_direct(n: int, p: int, k: float) -> np.ndarray:
     """Restriction of F^{-1}_{np}(ghat_grid) to Omega_{2n}, returned as a 2n-periodic array."""
     M = n * p
-    full = np.fft.ifftn(ghat_grid(n, p, k))
+    full = dft.ifftn(ghat_grid(n, p, k))
     idx = signed(2 * n) % M          # position of each signed k in Omega_{2n} inside the np grid
     return full[np.ix_(idx, idx, idx)]
 
@@ -69,7 +69,7 @@ def gm_coset(n: int, p: int, k: float) -> np.ndarray:
                 b = half * qp - s2
                 c = half * qp - s3
                 vals = green.ghat_t(delta * _radius3(a, b, c), k, R)
-                inv = np.fft.ifftn(vals)
+                inv = dft.ifftn(vals)
                 ph1 = np.exp(-2j * np.pi * kk * s1 / (n * p))
                 ph2 = np.exp(-2j * np.pi * kk * s2 / (n * p))
                 ph3 = np.exp(-2j * np.pi * kk * s3 / (n * p))
@@ -80,4 +80,4 @@ def gm_coset(n: int, p: int, k: float) -> np.ndarray:
 def ghat_m(n: int, p: int, k: float, method: str = "coset") -> np.ndarray:
     """F_{2n}(gm): the Fourier-domain kernel the volume operator multiplies by."""
     gm = gm_coset(n, p, k) if method == "coset" else gm_direct(n, p, k)
-    return np.fft.fftn(gm)
+    return dft.fftn(gm)

@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import dft
 from . import kernel as _kernel
 
 
@@ -41,14 +42,14 @@ def G_fft(ghat_m: np.ndarray, v: np.ndarray) -> np.ndarray:
     """Proposition 2 form on the 2n grid."""
     n = v.shape[0]
     assert ghat_m.shape == (2 * n,) * 3
-    w = np.fft.ifftn(ghat_m * np.fft.fftn(_embed(v, 2 * n)))
+    w = dft.ifftn(ghat_m * dft.fftn(_embed(v, 2 * n)))
     return _crop(w, n)
 
 
 def G_theorem1(n: int, p: int, k: float, v: np.ndarray) -> np.ndarray:
     """Theorem 1 form on the np grid."""
     gt = _kernel.ghat_grid(n, p, k)
-    w = np.fft.ifftn(gt * np.fft.fftn(_embed(v, n * p)))
+    w = dft.ifftn(gt * dft.fftn(_embed(v, n * p)))
     return _crop(w, n)
 
 

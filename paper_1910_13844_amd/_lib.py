@@ -18,7 +18,8 @@ LS_OP_FORWARD, LS_OP_FARFIELD, LS_OP_GRAD, LS_OP_APPLY, LS_OP_PROX, LS_OP_INCIDE
 # every symbol declared in include/ls.h
 EXPORTS = [
     "ls_strerror", "ls_last_error", "ls_kernel_bytes", "ls_init_workspace_bytes", "ls_green_init",
-    "ls_ctx_destroy", "ls_workspace_bytes", "ls_apply_G", "ls_apply_A", "ls_forward", "ls_farfield",
+    "ls_ctx_destroy", "ls_workspace_bytes", "ls_apply_G", "ls_apply_A", "ls_forward", "ls_forward_farfield",
+    "ls_farfield",
     "ls_farfield_adj", "ls_vjp", "ls_grad", "ls_batch_bytes", "ls_batch_create", "ls_batch_admit",
     "ls_batch_step", "ls_batch_poll", "ls_batch_release", "ls_batch_destroy", "ls_profile_pass",
     "ls_residual", "ls_grad_accumulate", "ls_prox_tv", "ls_fbs_extrapolate", "ls_tv_value",
@@ -34,7 +35,7 @@ class Geom(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("max_restarts", C.c_int32), ("x0_mode", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("breakdown", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -73,6 +74,7 @@ def load() -> C.CDLL:
         "ls_apply_G": (C.c_int, [vp, vp, vp, i32, vp, sz, vp]),
         "ls_apply_A": (C.c_int, [vp, vp, vp, vp, i32, vp, sz, vp]),
         "ls_forward": (C.c_int, [vp, vp, i32, dp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
+        "ls_forward_farfield": (C.c_int, [vp, vp, i32, dp, vp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
         "ls_farfield": (C.c_int, [vp, vp, vp, i32, vp, vp, sz, vp]),
         "ls_farfield_adj": (C.c_int, [vp, vp, i32, i32, vp, vp, sz, vp]),
         "ls_vjp": (C.c_int, [vp, vp, vp, i32, vp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
@@ -85,7 +87,7 @@ def load() -> C.CDLL:
         "ls_batch_release": (C.c_int, [vp, i32]),
         "ls_batch_destroy": (None, [vp]),
         "ls_profile_pass": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, sz, vp]),
-        "ls_residual": (C.c_int, [vp, vp, vp, i32, vp, vp, vp]),
+        "ls_residual": (C.c_int, [vp, vp, vp, i32, i32, vp, vp, vp, vp]),
         "ls_grad_accumulate": (C.c_int, [vp, vp, vp, i32, vp, vp, i32, vp]),
         "ls_prox_tv": (C.c_int, [vp, vp, vp, C.c_double, C.c_double, i32, i32, vp, vp, sz, vp]),
         "ls_fbs_extrapolate": (C.c_int, [vp, vp, vp, C.c_double, vp, vp]),

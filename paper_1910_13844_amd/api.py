@@ -105,8 +105,8 @@ class Context:
         return self._chk_like(y.contiguous(), (Q, self.n, self.n), self.cdtype, name)
 
     @staticmethod
-    def _opts(tol: float, maxit: int, max_restarts: int, x0_mode: int = 0) -> L.SolveOpts:
-        return L.SolveOpts(float(tol), int(maxit), int(max_restarts), int(x0_mode), 0)
+    def _opts(tol: float, maxit: int, max_restarts: int, x0_mode: int = 0, breakdown: float = 0.0) -> L.SolveOpts:
+        return L.SolveOpts(float(tol), int(maxit), int(max_restarts), int(x0_mode), 0, float(breakdown))
 
     # -- operators -------------------------------------------------------------------------
     def ls_apply_G(self, v: torch.Tensor, stream=None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -129,9 +129,10 @@ class Context:
 
     def ls_forward(self, f: torch.Tensor, dirs, tol: float = 1e-5, maxit: int = 500, max_restarts: int = 3,
                    u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None,
-                   warm_start: bool = False) -> Tuple[torch.Tensor, List[dict]]:
+                   warm_start: bool = False, breakdown: float = 0.0) -> Tuple[torch.Tensor, List[dict]]:
         """Forward solves for plane waves `dirs`.  warm_start: start BiCGSTAB from the contents of
-        `u` (which must then be given) instead of from the incident field."""
+        `u` (which must then be given) instead of from the incident field.  breakdown: threshold of
+        the restart test (0: the unit roundoff of the field precision)."""
         f = self._chk_f(f)
         if warm_start and u is None:
             raise ValueError("warm_start needs u (the initial guesses)")
@@ -142,15 +143,40 @@ class Context:
         self._chk_like(u, (Q, self.n, self.n, self.n), self.cdtype, "u")
         ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
         info = (L.SolveInfo * Q)()
-        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0)
+        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0, breakdown)
         L.check(self.lib.ls_forward(self.h, _ptr(f), Q, d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(u),
                                     C.byref(o), info, _ptr(ws), ws.numel(), _stream(stream)), "ls_forward")
         return u, [i.as_dict() for i in info]
 
+    def ls_forward_farfield(self, f: torch.Tensor, dirs, tol: float = 1e-5, maxit: int = 500, max_restarts: int = 3,
+                            u: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None,
+                            ws: Optional[torch.Tensor] = None, stream=None, warm_start: bool = False,
+                            breakdown: float = 0.0) -> Tuple[torch.Tensor, torch.Tensor, List[dict]]:
+        """ls_forward and the far field of every solution in one call: (u, y, info)."""
+        f = self._chk_f(f)
+        if warm_start and u is None:
+            raise ValueError("warm_start needs u (the initial guesses)")
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        Q = d.shape[0]
+        if u is None:
+            u = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device)
+        self._chk_like(u, (Q, self.n, self.n, self.n), self.cdtype, "u")
+        if y is None:
+            y = torch.empty((Q, self.n, self.n), dtype=self.cdtype, device=self.device)
+        self._chk_like(y, (Q, self.n, self.n), self.cdtype, "y")
+        ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
+        info = (L.SolveInfo * Q)()
+        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0, breakdown)
+        L.check(self.lib.ls_forward_farfield(self.h, _ptr(f), Q, d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(u),
+                                             _ptr(y), C.byref(o), info, _ptr(ws), ws.numel(), _stream(stream)),
+                "ls_forward_farfield")
+        return u, y, [i.as_dict() for i in info]
+
     def ls_forward_uin(self, f: torch.Tensor, uin: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
                        max_restarts: int = 3, u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-                       stream=None, warm_start: bool = False) -> Tuple[torch.Tensor, List[dict]]:
-        """Forward solves with stored incident volumes uin [Q, n, n, n] (warm_start as in ls_forward)."""
+                       stream=None, warm_start: bool = False, breakdown: float = 0.0) -> Tuple[torch.Tensor, List[dict]]:
+        """Forward solves with stored incident volumes uin [Q, n, n, n] (warm_start, breakdown as in
+        ls_forward)."""
         f = self._chk_f(f)
         if warm_start and u is None:
             raise ValueError("warm_start needs u (the initial guesses)")
@@ -161,7 +187,7 @@ class Context:
         self._chk_like(u, tuple(uin.shape), self.cdtype, "u")
         ws = self.workspace(Q, L.LS_OP_FORWARD) if ws is None else ws
         info = (L.SolveInfo * Q)()
-        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0)
+        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0, breakdown)
         L.check(self.lib.ls_forward_uin(self.h, _ptr(f), Q, _ptr(uin), _ptr(u), C.byref(o), info, _ptr(ws), ws.numel(),
                                         _stream(stream)), "ls_forward_uin")
         return u, [i.as_dict() for i in info]
@@ -194,13 +220,14 @@ class Context:
                 "ls_farfield")
         return y
 
-    def ls_farfield_adj(self, r: torch.Tensor, conj: bool = False, stream=None) -> torch.Tensor:
+    def ls_farfield_adj(self, r: torch.Tensor, conj: bool = False, stream=None,
+                        ws: Optional[torch.Tensor] = None) -> torch.Tensor:
         r = r.contiguous()
         if r.dtype != self.cdtype or r.device != self.device or r.shape[-2:] != (self.n, self.n):
             raise ValueError(f"r: expected [Q, n, n] in the field precision on {self.device}")
         Q = r.numel() // (self.n * self.n)
         out = torch.empty((Q, self.n, self.n, self.n), dtype=self.cdtype, device=self.device)
-        ws = self.workspace(Q, L.LS_OP_FARFIELD)
+        ws = self.workspace(Q, L.LS_OP_FARFIELD) if ws is None else ws
         L.check(self.lib.ls_farfield_adj(self.h, _ptr(r), int(bool(conj)), Q, _ptr(out), _ptr(ws), ws.numel(),
                                          _stream(stream)), "ls_farfield_adj")
         return out
@@ -237,18 +264,21 @@ class Context:
                                  _stream(stream)), "ls_grad")
         return loss.value, grad, [i.as_dict() for i in info]
 
-    def ls_residual(self, y: torch.Tensor, y_meas: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None
-                    ) -> Tuple[torch.Tensor, torch.Tensor]:
-        """r = y - y_meas and FP64 [||r_q||^2, ||y_meas_q||^2] per illumination."""
+    def ls_residual(self, y: torch.Tensor, y_meas: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    weighted: bool = False, stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+        """r = y - y_meas (weighted: (y - y_meas) / ||y_meas_q||^2), the FP64 sums
+        [||y_q - y_meas_q||^2, ||y_meas_q||^2] per illumination, and the data term of eq. (prob)
+        as a 0-dim float64 device tensor."""
         y = y.contiguous()
         Q = y.numel() // (self.n * self.n)
         y = self._chk_det_q(y, Q, "y")
         y_meas = self._chk_det_q(y_meas, Q, "y_meas")
         r = torch.empty_like(y) if out is None else self._chk_det_q(out, Q, "out")
         stats = torch.empty(2 * Q, dtype=torch.float64, device=self.device)
-        L.check(self.lib.ls_residual(self.h, _ptr(y), _ptr(y_meas), Q, _ptr(r), _ptr(stats), _stream(stream)),
-                "ls_residual")
-        return r, stats
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        L.check(self.lib.ls_residual(self.h, _ptr(y), _ptr(y_meas), Q, 1 if weighted else 0, _ptr(r), _ptr(stats),
+                                     _ptr(loss), _stream(stream)), "ls_residual")
+        return r, stats, loss
 
     def ls_grad_accumulate(self, u: torch.Tensor, wb: torch.Tensor, grad: torch.Tensor,
                            stats: Optional[torch.Tensor] = None, accumulate: bool = False, stream=None) -> torch.Tensor:

@@ -78,8 +78,24 @@ def detector_fields(f: torch.Tensor, lsctx: Context, dirs: Sequence, m: int, na=
     return LSDetector.apply(f, lsctx, dirs, m, na, dz, q, tol, maxit)
 
 
-def data_loss(y: torch.Tensor, y_meas: torch.Tensor) -> torch.Tensor:
-    """sum_q ||y_q - ymeas_q||^2 / (2 ||ymeas_q||^2), the data term of eq. (prob)."""
-    r = (y - y_meas).reshape(y.shape[0], -1)
-    m = y_meas.reshape(y.shape[0], -1)
-    return (r.abs() ** 2).sum(dim=1).div(2.0 * (m.abs() ** 2).sum(dim=1)).sum()
+class DataTerm(torch.autograd.Function):
+    """The data term of eq. (prob), L = sum_q ||y_q - ymeas_q||^2 / (2 ||ymeas_q||^2), computed by
+    ls_residual, which also returns its gradient with respect to y, (y_q - ymeas_q) / ||ymeas_q||^2
+    (PyTorch's dL/dRe(y) + i dL/dIm(y))."""
+
+    @staticmethod
+    def forward(ctx, y: torch.Tensor, y_meas: torch.Tensor, lsctx: Context):
+        gy, _, loss = lsctx.ls_residual(y.detach(), y_meas, weighted=True)
+        ctx.save_for_backward(gy)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (gy,) = ctx.saved_tensors
+        return g.to(gy.real.dtype) * gy, None, None
+
+
+def data_loss(y: torch.Tensor, y_meas: torch.Tensor, lsctx: Context) -> torch.Tensor:
+    """sum_q ||y_q - ymeas_q||^2 / (2 ||ymeas_q||^2), the data term of eq. (prob) (a 0-dim float64
+    tensor on the device), differentiable in y."""
+    return DataTerm.apply(y, y_meas, lsctx)

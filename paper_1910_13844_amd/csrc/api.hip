@@ -49,6 +49,8 @@ constexpr uint32_t M_RUN = 1u << ST_RUN;
 constexpr uint32_t M_HALF = 1u << ST_HALF;
 constexpr uint32_t M_CHECK = 1u << ST_CHECK;
 constexpr uint32_t M_INIT = 1u << ST_INIT;
+// Finished slots whose last x-forward may not be that of f . x (see farfield_after_solve).
+constexpr uint32_t M_STOPPED = (1u << ST_BREAK) | (1u << ST_NONFIN);
 constexpr uint32_t M_ALL = (1u << ST_RUN) | (1u << ST_HALF) | (1u << ST_CHECK) | (1u << ST_OK) | (1u << ST_MAXIT) |
                            (1u << ST_BREAK) | (1u << ST_NONFIN) | (1u << ST_INIT);
 
@@ -159,11 +161,13 @@ int scalar(const Run& r, int kind, uint32_t mask) {
   return LS_OK;
 }
 
-// Enqueue: initial residuals of admitted slots, then `iters` BiCGSTAB iterations, each followed
-// by the true-residual check of slots whose recursion finished.  Slots not in the state a kernel
-// acts on return immediately, so this needs no host round trip.  Only the host admits slots, so
-// it knows whether any is waiting for its initial residual (`init`); if none is, those launches
-// are skipped.
+// Enqueue: initial residuals of admitted slots, then `iters` BiCGSTAB iterations, then the
+// true-residual check of the slots whose recursion finished during them.  Slots not in the state
+// a kernel acts on return immediately, so this needs no host round trip; a slot that finishes its
+// recursion before the last of the iterations waits (untouched) for the check, so each slot runs
+// the same operations in the same order as with a check after every iteration.  Only the host
+// admits slots, so it knows whether any is waiting for its initial residual (`init`); if none is,
+// those launches are skipped.
 int enqueue_steps(const Run& r, int iters, bool init) {
   int rc;
   if (init) {
@@ -185,6 +189,8 @@ int enqueue_steps(const Run& r, int iters, bool init) {
       HIPCHK(launch_update(r.c->dbl, r.c->n, a, r.s));
     }
     if ((rc = scalar(r, SC_BETA, M_RUN | M_HALF))) return rc;
+  }
+  if (iters > 0) {
     if ((rc = matvec(r, PRO_F_VEC, V_X, EPI_TRUE, 0, 0, M_CHECK))) return rc;
     if ((rc = scalar(r, SC_FINAL, M_CHECK))) return rc;
   }
@@ -241,10 +247,17 @@ void to_info(const SlotState& s, double clk_khz, ls_solve_info* o) {
   o->time_ms = (s.t_done > s.t_start && s.t_start > 0 && clk_khz > 0) ? (double)(s.t_done - s.t_start) / clk_khz : -1.0;
 }
 
-SlotState init_state(const ls_solve_opts* o, int status) {
+// Breakdown threshold of a solve: the caller's, or the unit roundoff of the field precision.
+double breakdown_of(const ls_solve_opts& o, bool dbl) {
+  if (o.breakdown > 0.0) return o.breakdown;
+  return dbl ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+}
+
+SlotState init_state(const ls_solve_opts* o, int status, bool dbl) {
   SlotState s;
   std::memset(&s, 0, sizeof(s));
   s.tol = o->tol;
+  s.brk = breakdown_of(*o, dbl);
   s.maxit = o->maxit;
   s.max_restarts = o->max_restarts;
   s.status = status;
@@ -257,7 +270,9 @@ SlotState run_state() {
   o.maxit = 1;
   o.max_restarts = 0;
   o.x0_mode = 0;
-  return init_state(&o, ST_RUN);
+  o.reserved = 0;
+  o.breakdown = 0.0;
+  return init_state(&o, ST_RUN, false);
 }
 
 ls_solve_opts opts_or_default(const ls_solve_opts* o) {
@@ -266,12 +281,15 @@ ls_solve_opts opts_or_default(const ls_solve_opts* o) {
   d.maxit = 500;
   d.max_restarts = 3;
   d.x0_mode = 0;
+  d.reserved = 0;
+  d.breakdown = 0.0;
   if (o) d = *o;
   return d;
 }
 
 bool opts_ok(const ls_solve_opts& o) {
-  return o.tol > 0.0 && std::isfinite(o.tol) && o.maxit >= 1 && o.max_restarts >= 0 && (o.x0_mode == 0 || o.x0_mode == 1);
+  return o.tol > 0.0 && std::isfinite(o.tol) && o.maxit >= 1 && o.max_restarts >= 0 && (o.x0_mode == 0 || o.x0_mode == 1) &&
+         o.breakdown >= 0.0 && o.breakdown < 1.0;
 }
 
 char* vptr(const ls_ctx* c, char* ws, const WsLayout& L, int slot, int k) {
@@ -318,14 +336,16 @@ void bind_solver(const ls_ctx* c, char* ws, const WsLayout& L, int slot, int k0,
 
 int check_ctx(const ls_ctx* c) { return c && c->kbuf ? LS_OK : LS_ERR_ARG; }
 
-// far field of slot vectors: spectrum of f.vec[sel] -> k_ff -> detector vec[out_sel]
-int farfield_run(const Run& r, int sel, int tmp_sel, int out_sel, uint32_t mask) {
+// far field of slot vectors: spectrum of f.vec[sel] -> k_ff -> detector vec[out_sel].  The
+// x-forward runs on the slots in xfwd_mask only (the others already hold that spectrum in V_SPEC).
+int farfield_run(const Run& r, int sel, int tmp_sel, int out_sel, uint32_t mask, uint32_t xfwd_mask) {
   PassArgs a = r.base();
-  a.mask = mask;
+  a.mask = xfwd_mask;
   a.mode = PRO_F_VEC;
   a.sel = sel;
   a.spec = V_SPEC;
-  HIPCHK(launch_xfwd(r.c->dbl, r.c->n, a, r.s));
+  if (xfwd_mask) HIPCHK(launch_xfwd(r.c->dbl, r.c->n, a, r.s));
+  a.mask = mask;
   a.kern = r.c->kff;
   a.spec = V_SPEC;
   a.sel = tmp_sel;
@@ -357,6 +377,16 @@ int farfield_adj_run(const Run& r, int in_sel, int tmp_sel, int out_sel, bool co
   a.spec = V_SPEC;
   HIPCHK(launch_xinv(r.c->dbl, r.c->n, a, r.s));
   return LS_OK;
+}
+
+// Far field of the solutions of a finished solve into vec[out_sel].  A slot that ended through the
+// initial residual test or the final true-residual check last ran the x-forward of f . x, so its
+// V_SPEC already holds the x-spectrum the far field starts from (the same kernel on the same input
+// as a separate x-forward: bit for bit the same spectrum); slots that stopped inside the recursion
+// (breakdown, non-finite values), or all slots when some x was overwritten after the solve
+// (`recompute`), get it recomputed.  V_T (free once the solve is done) holds the detector spectra.
+int farfield_after_solve(const Run& r, int out_sel, bool recompute) {
+  return farfield_run(r, V_X, V_T, out_sel, M_ALL, recompute ? M_ALL : M_STOPPED);
 }
 
 }  // namespace
@@ -606,9 +636,11 @@ int ls_apply_A(const ls_ctx* ctx, const void* f, const void* v, void* out, int32
   return apply_common(ctx, f, v, out, Q, ws, ws_bytes, stream, true);
 }
 
-// Forward solves with plane-wave (dirs) or stored (uin) incident fields.
+// Forward solves with plane-wave (dirs) or stored (uin) incident fields; with y, also the far
+// field of every solution.
 static int forward_common(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, const void* uin, void* u,
-                          const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+                          void* y, const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes,
+                          void* stream) {
   const ls_solve_opts o = opts_or_default(opts);
   if (!opts_ok(o)) return LS_ERR_ARG;
   const int Qg = fit_slots(c, Q, LS_OP_FORWARD, ws_bytes);
@@ -620,11 +652,12 @@ static int forward_common(const ls_ctx* c, const void* f, int32_t Q, const doubl
     const int nq = std::min(Qg, Q - q0);
     const WsLayout L = ws_layout(c, nq, LS_OP_FORWARD);
     std::vector<SlotDesc> d(nq);
-    std::vector<SlotState> st(nq, init_state(&o, ST_INIT));
+    std::vector<SlotState> st(nq, init_state(&o, ST_INIT, c->dbl));
     for (int i = 0; i < nq; ++i) {
       d[i] = blank_desc(c, f);
       d[i].vec[V_X] = (char*)u + (size_t)(q0 + i) * c->N * c->csz;
       bind_solver(c, w, L, i, 0, d[i]);
+      if (y) d[i].vec[V_AUX] = (char*)y + (size_t)(q0 + i) * c->n * c->n * c->csz;
       if (uin)
         d[i].vec[V_B] = (void*)((const char*)uin + (size_t)(q0 + i) * c->N * c->csz);
       else
@@ -635,6 +668,16 @@ static int forward_common(const ls_ctx* c, const void* f, int32_t Q, const doubl
     int rc = upload(r, d, &st);
     if (rc) return rc;
     if ((rc = solve_all(r, h))) return rc;
+    // A zero right-hand side has the solution zero; a warm start would otherwise hand back the
+    // caller's guess, since the initial residual test accepts ||b|| = 0 before any update.
+    bool zeroed = false;
+    if (r.warm)
+      for (int i = 0; i < nq; ++i)
+        if (h[i].status == ST_OK && h[i].nb == 0.0) {
+          HIPCHK(hipMemsetAsync(d[i].vec[V_X], 0, c->N * c->csz, s));
+          zeroed = true;
+        }
+    if (y && (rc = farfield_after_solve(r, V_AUX, zeroed))) return rc;
     if (info)
       for (int i = 0; i < nq; ++i) to_info(h[i], c->clk_khz, info + q0 + i);
   }
@@ -644,13 +687,19 @@ static int forward_common(const ls_ctx* c, const void* f, int32_t Q, const doubl
 int ls_forward(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, void* u, const ls_solve_opts* opts,
                ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   if (check_ctx(c) || !f || !dirs || !u || !ws || Q < 1) return LS_ERR_ARG;
-  return forward_common(c, f, Q, dirs, nullptr, u, opts, info, ws, ws_bytes, stream);
+  return forward_common(c, f, Q, dirs, nullptr, u, nullptr, opts, info, ws, ws_bytes, stream);
+}
+
+int ls_forward_farfield(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, void* u, void* y,
+                        const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (check_ctx(c) || !f || !dirs || !u || !y || !ws || Q < 1) return LS_ERR_ARG;
+  return forward_common(c, f, Q, dirs, nullptr, u, y, opts, info, ws, ws_bytes, stream);
 }
 
 int ls_forward_uin(const ls_ctx* c, const void* f, int32_t Q, const void* uin, void* u, const ls_solve_opts* opts,
                    ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   if (check_ctx(c) || !f || !uin || !u || !ws || Q < 1 || uin == u) return LS_ERR_ARG;
-  return forward_common(c, f, Q, nullptr, uin, u, opts, info, ws, ws_bytes, stream);
+  return forward_common(c, f, Q, nullptr, uin, u, nullptr, opts, info, ws, ws_bytes, stream);
 }
 
 int ls_farfield(const ls_ctx* c, const void* f, const void* u, int32_t Q, void* y, void* ws, size_t ws_bytes,
@@ -676,7 +725,7 @@ int ls_farfield(const ls_ctx* c, const void* f, const void* u, int32_t Q, void* 
     Run r = make_run(c, w, L, nq, 0, s);
     int rc = upload(r, d, &st);
     if (rc) return rc;
-    if ((rc = farfield_run(r, V_X, V_T, V_AUX, M_RUN))) return rc;
+    if ((rc = farfield_run(r, V_X, V_T, V_AUX, M_RUN, M_RUN))) return rc;
   }
   return LS_OK;
 }
@@ -753,7 +802,7 @@ static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* 
     }
     Run rf = make_run(c, w, L, nq, 0, s);
     Run ra = make_run(c, w, L, nq, 1, s);
-    std::vector<SlotState> st(nq, init_state(&o, ST_INIT));
+    std::vector<SlotState> st(nq, init_state(&o, ST_INIT, c->dbl));
     if ((rc = upload(rf, dfw, &st))) return rc;
     if ((rc = upload(ra, dad, nullptr))) return rc;
     HIPCHK(hipMemcpyWithStream(w + L.off_desc[2], dgr.data(), sizeof(SlotDesc) * nq, hipMemcpyHostToDevice, s));
@@ -762,9 +811,9 @@ static int grad_driver(const ls_ctx* c, const void* f, int32_t Q, const double* 
       if (info)
         for (int i = 0; i < nq; ++i) to_info(h[i], c->clk_khz, info + q0 + i);
       // y = G~(f . u) into the detector buffer, then r = y - y_meas in place with FP64 norms
-      if ((rc = farfield_run(rf, V_X, V_T, V_AUX, M_ALL))) return rc;
-      HIPCHK(launch_residual(c->dbl, c->n, det, (const char*)y_meas + (size_t)q0 * M * c->csz, nq, det,
-                             d_stats, s));
+      if ((rc = farfield_after_solve(rf, V_AUX, false))) return rc;
+      HIPCHK(launch_residual(c->dbl, c->n, det, (const char*)y_meas + (size_t)q0 * M * c->csz, nq, false, det,
+                             d_stats, nullptr, s));
       std::vector<double> hs(2 * nq);
       HIPCHK(hipMemcpyAsync(hs.data(), d_stats, sizeof(double) * 2 * nq, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -956,7 +1005,7 @@ int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32
   char* w = (char*)ws;
   std::vector<SlotDesc> d(Q);
   ls_solve_opts o = opts_or_default(nullptr);
-  SlotState st0 = init_state(&o, ST_RUN);
+  SlotState st0 = init_state(&o, ST_RUN, c->dbl);
   st0.alpha[0] = st0.omega[0] = st0.beta[0] = 0.5;
   std::vector<SlotState> st(Q, st0);
   for (int i = 0; i < Q; ++i) {
@@ -986,10 +1035,10 @@ int ls_profile_pass(const ls_ctx* c, const void* f, void* u, int32_t pass, int32
   return LS_OK;
 }
 
-int ls_residual(const ls_ctx* c, const void* y, const void* y_meas, int32_t Q, void* r, double* stats,
-                void* stream) {
+int ls_residual(const ls_ctx* c, const void* y, const void* y_meas, int32_t Q, int32_t weighted, void* r,
+                double* stats, double* loss, void* stream) {
   if (check_ctx(c) || !y || !y_meas || !r || !stats || Q < 1) return LS_ERR_ARG;
-  HIPCHK(launch_residual(c->dbl, c->n, y, y_meas, Q, r, stats, (hipStream_t)stream));
+  HIPCHK(launch_residual(c->dbl, c->n, y, y_meas, Q, weighted != 0, r, stats, loss, (hipStream_t)stream));
   return LS_OK;
 }
 
@@ -1037,7 +1086,7 @@ int ls_batch_create(const ls_ctx* c, int32_t nslots, void* ws, size_t ws_bytes, 
   b->L = L;
   b->o = o;
   b->hd.assign(nslots, blank_desc(c, nullptr));
-  b->hs.assign(nslots, init_state(&o, ST_IDLE));
+  b->hs.assign(nslots, init_state(&o, ST_IDLE, c->dbl));
   for (int i = 0; i < nslots; ++i) bind_solver(c, b->ws, L, i, 0, b->hd[i]);
   Run r = make_run(c, b->ws, L, nslots, 0, nullptr);
   int rc = upload(r, b->hd, &b->hs);
@@ -1059,7 +1108,7 @@ int ls_batch_admit(ls_batch* b, int32_t slot, const void* f, const double* dir, 
   d.vec[V_X] = x;
   d.vec[V_B] = (void*)rhs;
   for (int j = 0; j < 3; ++j) d.d[j] = dir ? dir[j] : 0.0;
-  b->hs[slot] = init_state(&b->o, ST_INIT);
+  b->hs[slot] = init_state(&b->o, ST_INIT, b->c->dbl);
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipMemcpyWithStream((SlotDesc*)(b->ws + b->L.off_desc[0]) + slot, &d, sizeof(SlotDesc),
                              hipMemcpyHostToDevice, s));

@@ -47,6 +47,7 @@ enum Status : int32_t {
 struct SlotState {
   double rho[2], rho_prev[2], alpha[2], omega[2], beta[2];
   double nb, rr, nrh, relres, relres_true, tol;
+  double brk;  // breakdown threshold: restart when |rho| <= brk ||rh|| ||r||
   int32_t status, iters, matvecs, restarts, restart_flag, maxit, max_restarts, reason;
   uint64_t t_start, t_done;  // device steady clock: first pass of the slot, final state reached
 };

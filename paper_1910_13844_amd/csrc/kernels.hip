@@ -1241,10 +1241,10 @@ __device__ __forceinline__ bool final_state(int s) {
 }
 
 template <int KIND>
-__device__ __forceinline__ void scalar_update(SlotState& st, const double (&v)[6], double eps);
+__device__ __forceinline__ void scalar_update(SlotState& st, const double (&v)[6]);
 
 template <int KIND>
-__global__ __launch_bounds__(256) void k_scalar(PassArgs a, double eps) {
+__global__ __launch_bounds__(256) void k_scalar(PassArgs a) {
   __shared__ double red[6 * 4];
   const int slot = blockIdx.x;
   if (!slot_active(a, slot)) return;
@@ -1259,13 +1259,13 @@ __global__ __launch_bounds__(256) void k_scalar(PassArgs a, double eps) {
   if (tid != 0) return;
   SlotState& st = a.st[slot];
   const int s0 = st.status;
-  scalar_update<KIND>(st, v, eps);
+  scalar_update<KIND>(st, v);
   if (final_state(st.status) && !final_state(s0)) st.t_done = (uint64_t)wall_clock64();
 }
 
 // One step of the per-slot BiCGSTAB scalar recurrence from the block-summed partials v.
 template <int KIND>
-__device__ __forceinline__ void scalar_update(SlotState& st, const double (&v)[6], double eps) {
+__device__ __forceinline__ void scalar_update(SlotState& st, const double (&v)[6]) {
   const cplx<double> p0 = {v[0], v[1]}, p1 = {v[2], v[3]}, p2 = {v[4], v[5]};
   if (KIND == SC_INIT) {
     st.matvecs += 1;
@@ -1336,7 +1336,7 @@ __device__ __forceinline__ void scalar_update(SlotState& st, const double (&v)[6
     }
     cplx<double> rho = p0;
     const bool om_zero = st.omega[0] == 0.0 && st.omega[1] == 0.0;
-    if (om_zero || sqrt(rho.re * rho.re + rho.im * rho.im) <= eps * st.nrh * st.rr) {
+    if (om_zero || sqrt(rho.re * rho.re + rho.im * rho.im) <= st.brk * st.nrh * st.rr) {
       st.restarts += 1;
       fresh_restart(st);
       rho = getc(st.rho);
@@ -1403,26 +1403,55 @@ __global__ __launch_bounds__(256) void k_convert(const double* src, T* dst, size
   if (i < N) dst[i] = (T)src[i];
 }
 
-// r = y - ymeas per view and FP64 ||r||^2, ||ymeas||^2 (one block per view, fixed order).
-template <typename T>
+// r = w_q (y - ymeas) per view with FP64 ||y - ymeas||^2 and ||ymeas||^2 (one block per view, fixed
+// order); w_q = 1, or 1 / ||ymeas_q||^2 when WEIGHTED (then ||ymeas||^2 is summed in a first sweep).
+template <typename T, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_residual(const cplx<T>* y, const cplx<T>* ym, int M, cplx<T>* r,
                                                   double* stats) {
   __shared__ double red[2 * 4];
+  __shared__ double nym;
   const int q = blockIdx.x;
   double v[2] = {0, 0};
+  T w = (T)1;
+  if (WEIGHTED) {
+    double s1[1] = {0.0};
+    for (int i = threadIdx.x; i < M; i += 256) {
+      const cplx<T> b = ym[(size_t)q * M + i];
+      s1[0] += (double)b.re * b.re + (double)b.im * b.im;
+    }
+    block_sum<1>(s1, red);
+    if (threadIdx.x == 0) nym = s1[0];
+    __syncthreads();
+    v[1] = nym;
+    w = (T)(1.0 / v[1]);
+  }
   for (int i = threadIdx.x; i < M; i += 256) {
     const size_t idx = (size_t)q * M + i;
     const cplx<T> a = y[idx], b = ym[idx];
     const cplx<T> d = a - b;
-    r[idx] = d;
+    r[idx] = WEIGHTED ? cplx<T>{d.re * w, d.im * w} : d;
     v[0] += (double)d.re * d.re + (double)d.im * d.im;
-    v[1] += (double)b.re * b.re + (double)b.im * b.im;
+    if (!WEIGHTED) v[1] += (double)b.re * b.re + (double)b.im * b.im;
   }
-  block_sum<2>(v, red);
+  if (WEIGHTED) {
+    double s0[1] = {v[0]};
+    block_sum<1>(s0, red);
+    v[0] = s0[0];
+  } else {
+    block_sum<2>(v, red);
+  }
   if (threadIdx.x == 0) {
     stats[2 * q] = v[0];
     stats[2 * q + 1] = v[1];
   }
+}
+
+// Data term of eq. (prob) from the per-view sums: sum_q stats[2q] / (2 stats[2q+1]) in q order.
+__global__ void k_data_loss(const double* stats, int Q, double* loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int q = 0; q < Q; ++q) s += stats[2 * q] / (2.0 * stats[2 * q + 1]);
+  *loss = s;
 }
 
 // =============================================================================================
@@ -1548,13 +1577,13 @@ hipError_t launch_ffT(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DI
 hipError_t launch_update(bool dbl, int n, const PassArgs& a, hipStream_t s) { LS_DISPATCH(update_t, dbl, n, a, s) }
 
 hipError_t launch_scalar(int kind, bool dbl, const PassArgs& a, hipStream_t s) {
-  const double eps = dbl ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+  (void)dbl;
   switch (kind) {
-    case SC_INIT: hipLaunchKernelGGL(k_scalar<SC_INIT>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
-    case SC_ALPHA: hipLaunchKernelGGL(k_scalar<SC_ALPHA>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
-    case SC_OMEGA: hipLaunchKernelGGL(k_scalar<SC_OMEGA>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
-    case SC_BETA: hipLaunchKernelGGL(k_scalar<SC_BETA>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
-    case SC_FINAL: hipLaunchKernelGGL(k_scalar<SC_FINAL>, dim3(a.nslots), dim3(256), 0, s, a, eps); break;
+    case SC_INIT: hipLaunchKernelGGL(k_scalar<SC_INIT>, dim3(a.nslots), dim3(256), 0, s, a); break;
+    case SC_ALPHA: hipLaunchKernelGGL(k_scalar<SC_ALPHA>, dim3(a.nslots), dim3(256), 0, s, a); break;
+    case SC_OMEGA: hipLaunchKernelGGL(k_scalar<SC_OMEGA>, dim3(a.nslots), dim3(256), 0, s, a); break;
+    case SC_BETA: hipLaunchKernelGGL(k_scalar<SC_BETA>, dim3(a.nslots), dim3(256), 0, s, a); break;
+    case SC_FINAL: hipLaunchKernelGGL(k_scalar<SC_FINAL>, dim3(a.nslots), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1594,15 +1623,25 @@ hipError_t launch_convert(bool dbl, const double* src, void* dst, size_t N, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_residual(bool dbl, int m, const void* y, const void* ymeas, int Q, void* r, double* stats,
-                           hipStream_t s) {
+hipError_t launch_residual(bool dbl, int m, const void* y, const void* ymeas, int Q, bool weighted, void* r,
+                           double* stats, double* loss, hipStream_t s) {
   const int M = m * m;
-  if (dbl)
-    hipLaunchKernelGGL(k_residual<double>, dim3(Q), dim3(256), 0, s, (const cplx<double>*)y,
-                       (const cplx<double>*)ymeas, M, (cplx<double>*)r, stats);
-  else
-    hipLaunchKernelGGL(k_residual<float>, dim3(Q), dim3(256), 0, s, (const cplx<float>*)y, (const cplx<float>*)ymeas,
-                       M, (cplx<float>*)r, stats);
+  if (dbl) {
+    if (weighted)
+      hipLaunchKernelGGL((k_residual<double, true>), dim3(Q), dim3(256), 0, s, (const cplx<double>*)y,
+                         (const cplx<double>*)ymeas, M, (cplx<double>*)r, stats);
+    else
+      hipLaunchKernelGGL((k_residual<double, false>), dim3(Q), dim3(256), 0, s, (const cplx<double>*)y,
+                         (const cplx<double>*)ymeas, M, (cplx<double>*)r, stats);
+  } else {
+    if (weighted)
+      hipLaunchKernelGGL((k_residual<float, true>), dim3(Q), dim3(256), 0, s, (const cplx<float>*)y,
+                         (const cplx<float>*)ymeas, M, (cplx<float>*)r, stats);
+    else
+      hipLaunchKernelGGL((k_residual<float, false>), dim3(Q), dim3(256), 0, s, (const cplx<float>*)y,
+                         (const cplx<float>*)ymeas, M, (cplx<float>*)r, stats);
+  }
+  if (loss) hipLaunchKernelGGL(k_data_loss, dim3(1), dim3(64), 0, s, stats, Q, loss);
   return hipGetLastError();
 }
 

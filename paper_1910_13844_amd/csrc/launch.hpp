@@ -23,8 +23,8 @@ hipError_t launch_grad_accum(bool dbl, int n, const SlotDesc* desc, const double
 hipError_t launch_grad_sum(bool dbl, const void* u, const void* wb, int Q, size_t N, const double* stats, void* grad,
                            int accumulate, hipStream_t s);
 hipError_t launch_convert(bool dbl, const double* src, void* dst, size_t N, hipStream_t s);
-hipError_t launch_residual(bool dbl, int m, const void* y, const void* ymeas, int Q, void* r, double* stats,
-                           hipStream_t s);
+hipError_t launch_residual(bool dbl, int m, const void* y, const void* ymeas, int Q, bool weighted, void* r,
+                           double* stats, double* loss, hipStream_t s);
 
 // reconstruction step (recon.hip)
 hipError_t launch_prox_init(bool dbl, const void* v, const void* d, double gamma, void* z, void* p, void* r,

@@ -46,7 +46,7 @@ class WarmGradient:
         self.u, _ = ctx.ls_forward(f0, self.dirs, tol=tol)
         self.w = None
         if adjoint:
-            r, _ = ctx.ls_residual(ctx.ls_farfield(f0, self.u), y_meas)
+            r, _, _ = ctx.ls_residual(ctx.ls_farfield(f0, self.u), y_meas)
             self.w, _ = ctx.ls_forward_uin(f0, ctx.ls_farfield_adj(r, conj=True), tol=tol)
 
     def __call__(self, v: torch.Tensor, sub: Sequence[int]):
@@ -56,7 +56,7 @@ class WarmGradient:
         u, i_fw = c.ls_forward(v, self.dirs[list(sub)], tol=self.tol, u=self.u.index_select(0, idx),
                                warm_start=True)
         y = c.ls_farfield(v, u)
-        r, stats = c.ls_residual(y, self.y_meas.index_select(0, idx), out=y)
+        r, stats, loss = c.ls_residual(y, self.y_meas.index_select(0, idx), out=y)
         b = c.ls_farfield_adj(r, conj=True)
         if self.adjoint:
             w, i_ad = c.ls_forward_uin(v, b, tol=self.tol, u=self.w.index_select(0, idx), warm_start=True)
@@ -65,9 +65,7 @@ class WarmGradient:
             w, i_ad = c.ls_forward_uin(v, b, tol=self.tol)
         grad = c.ls_grad_accumulate(u, w, torch.empty_like(v), stats=stats)
         self.u.index_copy_(0, idx, u)
-        s = stats.cpu().numpy()
-        loss = float(sum(s[2 * i] / (2.0 * s[2 * i + 1]) for i in range(len(idx))))
-        return loss, grad, i_fw + i_ad
+        return float(loss), grad, i_fw + i_ad
 
 
 def reconstruct(ctx: Context, dirs, y_meas: torch.Tensor, f0: torch.Tensor, tau: float, gamma0: float,

@@ -9,6 +9,12 @@ field and residual, then one adjoint solve per illumination (right-hand side G~^
 gradient accumulation.  Each result is the same alone and in a mix: slots never interact (per-slot
 reductions in a fixed order).
 
+Admission is by device-memory footprint: the engine keeps a byte ledger (``Ledger``) over one
+budget shared by every pool -- the Green kernels and far-field workspaces of each grid size, the slot
+pools' workspaces, and every request's own fields (``request_bytes``).  A request's first job is
+admitted only when its fields fit in what the budget has left; until then it waits at the head of
+its pool's queue (no overtaking), and its bytes return to the budget when it completes.
+
 Engines: ``GpuEngine`` drives libls through ``api``; tests substitute a CPU engine with the same
 methods to exercise the scheduler without a GPU.
 
@@ -39,6 +45,7 @@ class Request:
     theta: float
     # filled by the loop
     done_time: Optional[float] = None
+    admitted: bool = False   # its fields hold device memory (first job admitted, not yet complete)
     outputs: dict = dataclasses.field(default_factory=dict)
 
 
@@ -66,11 +73,66 @@ def poisson_trace(nreq: int, rate: float, grids: Sequence[int], qmax: int = 60, 
     return out
 
 
+def request_bytes(kind: str, n: int, Q: int, csz: int) -> int:
+    """Device bytes a request holds from its first admission to its completion: the total fields u
+    (Q N complex) and detector fields y (Q n^2); for gradients also the adjoint solutions w and their
+    right-hand sides b (Q N each), the detector residuals (Q n^2), their FP64 sums (2Q) and the
+    gradient (N reals).  csz: bytes per complex (8 for complex64)."""
+    N, M = n ** 3, n * n
+    b = Q * (N + M) * csz
+    if kind == "grad":
+        b += Q * (2 * N + M) * csz + 2 * Q * 8 + N * (csz // 2)
+    return b
+
+
+class Ledger:
+    """A device-memory budget as named charges (thread-safe).  ``charge`` raises MemoryError when a
+    charge would exceed the budget; ``try_charge`` reports it instead; ``peak`` is the largest total
+    ever charged."""
+
+    def __init__(self, budget: float):
+        import threading
+        self.budget = int(budget)
+        self.charges: Dict[tuple, int] = {}
+        self.used = 0
+        self.peak = 0
+        self._lock = threading.Lock()
+
+    def try_charge(self, key: tuple, nbytes: int) -> bool:
+        with self._lock:
+            if key in self.charges:
+                raise KeyError(f"{key} is already charged")
+            if self.used + nbytes > self.budget:
+                return False
+            self.charges[key] = int(nbytes)
+            self.used += int(nbytes)
+            self.peak = max(self.peak, self.used)
+            return True
+
+    def charge(self, key: tuple, nbytes: int) -> None:
+        if not self.try_charge(key, nbytes):
+            raise MemoryError(f"{key}: {nbytes} bytes do not fit the device budget ({self.used} of "
+                              f"{self.budget} bytes in use)")
+
+    def release(self, key: tuple) -> int:
+        with self._lock:
+            nbytes = self.charges.pop(key)
+            self.used -= nbytes
+            return nbytes
+
+    def held(self, kinds: Sequence[str]) -> int:
+        """Total of the charges whose key starts with one of `kinds`."""
+        with self._lock:
+            return sum(v for k, v in self.charges.items() if k[0] in kinds)
+
+
 class Scheduler:
     """Continuous batching over per-grid-size slot pools.
 
     engine: object with
       pool_capacity(n) -> int
+      reserve(req) -> bool                  -> (optional) charge the request's device footprint;
+                                               False: it does not fit now, the request waits
       prepare(req)                          -> per-request device data (potential, directions, data)
       admit(n, slot, job)                   -> start the job's solve in `slot` of pool n
       step(n, iters)                        -> advance every running slot of pool n
@@ -107,12 +169,18 @@ class Scheduler:
 
     def _fill(self, n):
         slots = self.slots[n]
+        reserve = getattr(self.e, "reserve", None)
         for i, s in enumerate(slots):
             if s is None and self.pending[n]:
-                job = self.pending[n].popleft()
-                if job.phase == "fwd" and job.q == 0:
-                    # per-request device buffers exist only from the first admission to completion
+                job = self.pending[n][0]
+                if not job.req.admitted:
+                    # per-request device buffers exist only from the first admission to completion;
+                    # a request whose fields do not fit the memory left waits at the head of the queue
+                    if reserve is not None and not reserve(job.req):
+                        break
                     self.e.prepare(job.req)
+                    job.req.admitted = True
+                self.pending[n].popleft()
                 job.slot = i
                 self.e.admit(n, i, job)
                 slots[i] = job
@@ -146,6 +214,7 @@ class Scheduler:
 
     def _complete(self, req: Request, t0: float):
         req.done_time = self.clock() - t0
+        req.admitted = False
         self.completed.append(req)
         if self.progress and len(self.completed) % self.progress == 0:
             print(f"[serve] {len(self.completed)} requests done at {req.done_time:.1f} s", file=sys.stderr, flush=True)
@@ -201,17 +270,20 @@ class ConcurrentScheduler(Scheduler):
                 with (stream_context(n) if stream_context else contextlib.nullcontext()):
                     while True:
                         with cv:
-                            while state["error"] is None and not state["closed"] and not pool_busy(n):
+                            while True:
+                                if state["error"] is not None or (state["closed"] and not pool_busy(n)):
+                                    return
+                                if pool_busy(n):
+                                    self._fill(n)
+                                    if any(s is not None for s in self.slots[n]):
+                                        break
+                                # idle, or the queue's head waits for device memory that another
+                                # pool's completions will return (they notify)
                                 cv.wait(0.05)
-                            if state["error"] is not None or (state["closed"] and not pool_busy(n)):
-                                return
-                            self._fill(n)
-                            active = any(s is not None for s in self.slots[n])
-                        if active:
-                            self.e.step(n, self.iters)
-                            with cv:
-                                self._harvest(n, t0)
-                                cv.notify_all()
+                        self.e.step(n, self.iters)
+                        with cv:
+                            self._harvest(n, t0)
+                            cv.notify_all()
             except BaseException as exc:  # reported by run() after the threads have stopped
                 with cv:
                     state["error"] = exc
@@ -252,20 +324,32 @@ def summarize(done: Sequence[Request], total: float, solves: int) -> dict:
 
 # ---------------------------------------------------------------------------------------------
 class GpuEngine:
-    """Scheduler engine backed by libls on one GPU."""
+    """Scheduler engine backed by libls on one GPU, with every device buffer it allocates charged to
+    one budget (``ledger``): per grid size the Green kernels and a far-field workspace for
+    ``ff_group`` illuminations, the slot pool's workspace (pools share ``pool_fraction`` of the budget
+    evenly over the grid sizes served, at most ``max_slots`` slots each), and each admitted
+    request's fields (``request_bytes``).  Request inputs (potentials, directions, measurements)
+    are preloaded before the trace starts and are not part of the budget."""
 
     def __init__(self, hbm_budget_gb: float = 120.0, tol: float = 1e-5, maxit: int = 500, prec: str = "c64",
-                 device: str = "cuda:0", max_slots: int = 64, inputs: Optional[dict] = None):
+                 device: str = "cuda:0", max_slots: int = 64, inputs: Optional[dict] = None,
+                 grids: Optional[Sequence[int]] = None, pool_fraction: float = 0.5, ff_group: int = 8):
         import torch
 
         from . import _lib, api, workloads
 
         self.torch, self.api, self.wl, self._lib = torch, api, workloads, _lib
         self.tol, self.maxit, self.prec, self.device = tol, maxit, prec, device
-        self.budget = hbm_budget_gb * 1e9
+        self.ledger = Ledger(hbm_budget_gb * 1e9)
         self.max_slots = max_slots
+        self.pool_fraction = pool_fraction
+        self.ff_group = ff_group
+        self.grids: List[int] = sorted(set(grids)) if grids else []
+        self.csz = 8 if prec == "c64" else 16
         self.ctx: Dict[int, "api.Context"] = {}
+        self.ffws: Dict[int, "torch.Tensor"] = {}
         self.pool: Dict[int, "api.Batch"] = {}
+        self.cap: Dict[int, int] = {}
         self.data: Dict[int, dict] = {}
         self.streams: Dict[int, "torch.cuda.Stream"] = {}
         # request inputs (potential, directions, measurements) keyed by request id; may be shared
@@ -283,24 +367,57 @@ class GpuEngine:
 
     def _ctx(self, n):
         if n not in self.ctx:
-            self.ctx[n] = self.api.Context(n, self.wl.k_of(), p=4, xg=float(n), prec=self.prec, device=self.device)
+            c = self.api.Context(n, self.wl.k_of(), p=4, xg=float(n), prec=self.prec, device=self.device)
+            self.ledger.charge(("ctx", n), c.kbuf.numel())
+            nb = c.workspace_bytes(self.ff_group, self._lib.LS_OP_FARFIELD)
+            self.ledger.charge(("ws", n), nb)
+            self.ffws[n] = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+            self.ctx[n] = c
         return self.ctx[n]
 
     def pool_capacity(self, n):
+        if n in self.cap:
+            return self.cap[n]
+        if n not in self.grids:
+            self.grids.append(n)
         c = self._ctx(n)
         per_slot = c.workspace_bytes(2, self._lib.LS_OP_FORWARD) - c.workspace_bytes(1, self._lib.LS_OP_FORWARD)
-        share = self.budget / 3.0
-        cap = int(max(1, min(self.max_slots, share // max(per_slot, 1))))
-        self.pool[n] = self.api.Batch(c, cap, tol=self.tol, maxit=self.maxit)
+        share = self.pool_fraction * self.ledger.budget / max(1, len(self.grids))
+        cap = int(min(self.max_slots, share // max(per_slot, 1)))
+        if cap < 1:
+            raise MemoryError(f"grid {n}: one slot ({per_slot} bytes) exceeds the pool share of the budget")
+        pool = self.api.Batch(c, cap, tol=self.tol, maxit=self.maxit)
+        self.ledger.charge(("pool", n), pool.ws.numel())
+        self.pool[n], self.cap[n] = pool, cap
         return cap
+
+    def reserve(self, req: Request) -> bool:
+        nbytes = request_bytes(req.kind, req.n, req.Q, self.csz)
+        free_at_best = self.ledger.budget - self.ledger.held(("ctx", "ws", "pool"))
+        if nbytes > free_at_best:
+            raise MemoryError(f"request {req.rid}: {nbytes} bytes can never fit the budget ({free_at_best} bytes "
+                              "left beside the kernels and slot pools)")
+        return self.ledger.try_charge(("req", req.rid), nbytes)
+
+    def memory_report(self) -> dict:
+        return {"budget_bytes": self.ledger.budget, "peak_bytes": self.ledger.peak,
+                "fixed_bytes": self.ledger.held(("ctx", "ws", "pool")),
+                "torch_max_allocated_bytes": int(self.torch.cuda.max_memory_allocated(self.device))}
 
     def preload(self, trace: Sequence[Request], workers: int = 8):
         """Generate every request's inputs before the trace starts (not part of the served work):
         the potential, the illumination directions and, for gradient requests, synthetic measurements
-        of a perturbed phantom.  Phantoms are generated on `workers` host threads."""
+        of a perturbed phantom.  Phantoms are generated on `workers` host threads.  Also builds the
+        kernels and slot pools of every grid size in the trace, so the budget's fixed part is known
+        before the first admission."""
         import concurrent.futures as cf
 
         torch = self.torch
+        for n in sorted(set(r.n for r in trace)):
+            if n not in self.grids:
+                self.grids.append(n)
+        for n in sorted(set(r.n for r in trace)):
+            self.pool_capacity(n)
         todo = [r for r in trace if r.rid not in self.inputs]
 
         def phantoms(req):
@@ -321,7 +438,10 @@ class GpuEngine:
                     d["y_meas"] = c.ls_farfield(ft, ut)
                     del ut, ft
                 self.inputs[req.rid] = d
+        for c in self.ctx.values():   # scratch of the measurement solves
+            c._ws.clear()
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()
 
     def prepare(self, req: Request):
         c = self._ctx(req.n)
@@ -347,19 +467,23 @@ class GpuEngine:
     def release(self, n, slot):
         self.pool[n].ls_batch_release(slot)
 
+    def _done(self, req: Request):
+        self.data.pop(req.rid, None)
+        self.torch.cuda.current_stream().synchronize()   # the request is complete when its outputs are
+        self.ledger.release(("req", req.rid))
+
     def finish_forward(self, req: Request):
         c = self.ctx[req.n]
         d = self.data[req.rid]
-        d["y"] = c.ls_farfield(d["f"], d["u"])
+        ws = self.ffws[req.n]
+        d["y"] = c.ls_farfield(d["f"], d["u"], ws=ws)
         if req.kind == "grad":
-            r, d["stats"] = c.ls_residual(d["y"], d["y_meas"])
-            st = d["stats"].cpu().numpy()
-            d["loss"] = float(np.sum(st[0::2] / (2.0 * st[1::2])))
-            d["b"] = c.ls_farfield_adj(r, conj=True)
+            r, d["stats"], loss = c.ls_residual(d["y"], d["y_meas"])
+            d["loss"] = float(loss)
+            d["b"] = c.ls_farfield_adj(r, conj=True, ws=ws)
         else:
             req.outputs["y"] = d["y"]
-            self.data.pop(req.rid, None)
-            self.torch.cuda.current_stream().synchronize()   # the request is complete when its field is
+            self._done(req)
 
     def finish_grad(self, req: Request):
         d = self.data[req.rid]
@@ -367,8 +491,7 @@ class GpuEngine:
         g = self.torch.empty((req.n,) * 3, dtype=c.rdtype, device=self.device)
         req.outputs["grad"] = c.ls_grad_accumulate(d["u"], d["w"], g, stats=d["stats"])
         req.outputs["loss"] = d["loss"]
-        self.data.pop(req.rid, None)
-        self.torch.cuda.current_stream().synchronize()
+        self._done(req)
 
 
 def one_at_a_time(engine_factory, trace: Sequence[Request]) -> dict:
@@ -384,6 +507,8 @@ def one_at_a_time(engine_factory, trace: Sequence[Request]) -> dict:
         now = time.perf_counter() - t0
         if req.arrival > now:
             time.sleep(req.arrival - now)
+        if not e.reserve(req):
+            raise MemoryError(f"request {req.rid} does not fit the budget even alone")
         e.prepare(req)
         c = e._ctx(req.n)
         d = e.data[req.rid]
@@ -451,6 +576,7 @@ def main(argv=None) -> int:
     sched = (Scheduler if args.single_thread else ConcurrentScheduler)(eng, progress=50)
     res = {"continuous": sched.run(trace)}
     torch.cuda.synchronize()
+    res["continuous"]["memory"] = eng.memory_report()
     print(f"[serve] continuous: {res['continuous']}", file=sys.stderr, flush=True)
     if args.baseline:
         del sched, eng

@@ -131,7 +131,9 @@ WORKLOADS: Dict[str, Workload] = {
     "C": Workload("blobs256_q60_c64", 256, 4, 60, 45.0, 1e-5, "c64", "blobs", seed=1, dn_max=0.1),
     # 128^3 gradient workload, 40 illuminations on a 40 degree cone.
     # f0 = phantom seed 2; data from f0 + a 5-blob perturbation (seed 3) with 30 dB noise (seed 4).
-    "D": Workload("grad128_q40_c64", 128, 4, 40, 40.0, 1e-5, "c64", "blobs", seed=2, dn_max=0.05,
+    # Solver tolerance 1e-6: the gradient sums 40 views whose terms largely cancel, so at 1e-5 the
+    # solves alone leave it ~7e-4 from the exact one; 1e-6 brings it within 1e-4.
+    "D": Workload("grad128_q40_c64", 128, 4, 40, 40.0, 1e-6, "c64", "blobs", seed=2, dn_max=0.05,
                   kind="gradient"),
 }
 

@@ -85,8 +85,8 @@ def test_struct_layouts_match_the_header(tmp_path):
 #include "ls.h"
 int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(ls_geom), offsetof(ls_geom, kbh), offsetof(ls_geom, xg), offsetof(ls_geom, prec));
-  printf("%zu %zu %zu %zu\\n", sizeof(ls_solve_opts), offsetof(ls_solve_opts, maxit), offsetof(ls_solve_opts, max_restarts),
-         offsetof(ls_solve_opts, x0_mode));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(ls_solve_opts), offsetof(ls_solve_opts, maxit), offsetof(ls_solve_opts, max_restarts),
+         offsetof(ls_solve_opts, x0_mode), offsetof(ls_solve_opts, breakdown));
   printf("%zu %zu %zu %zu\\n", sizeof(ls_solve_info), offsetof(ls_solve_info, relres_rec),
          offsetof(ls_solve_info, relres_true), offsetof(ls_solve_info, time_ms));
   return 0;
@@ -100,6 +100,6 @@ int main(void) {
     i = [int(t) for t in lines[2].split()]
     assert g == [C.sizeof(L.Geom), L.Geom.kbh.offset, L.Geom.xg.offset, L.Geom.prec.offset]
     assert o == [C.sizeof(L.SolveOpts), L.SolveOpts.maxit.offset, L.SolveOpts.max_restarts.offset,
-                 L.SolveOpts.x0_mode.offset]
+                 L.SolveOpts.x0_mode.offset, L.SolveOpts.breakdown.offset]
     assert i == [C.sizeof(L.SolveInfo), L.SolveInfo.relres_rec.offset, L.SolveInfo.relres_true.offset,
                  L.SolveInfo.time_ms.offset]

@@ -29,7 +29,7 @@ def test_autograd_backward_matches_oracle_gradient():
     _, yhat = prob.forward(f0 + pert, dirs)
     f = torch.from_numpy(f0).to(DEV).requires_grad_(True)
     y = autograd.farfield(f, c, dirs, tol=1e-13)
-    loss = autograd.data_loss(y, torch.from_numpy(yhat).to(DEV))
+    loss = autograd.data_loss(y, torch.from_numpy(yhat).to(DEV), c)
     loss.backward()
     lo, go = prob.loss_grad(f0, dirs, yhat)
     assert abs(loss.item() - lo) <= 1e-10 * lo

@@ -116,3 +116,41 @@ def test_solve_256_c64_oracle_residual():
     rr = np.linalg.norm(b - ops.A_apply(ghat(n), f, u1)) / np.linalg.norm(b)
     print(f"[solve] iters={[i['iters'] for i in info]} oracle relres={rr:.2e}", flush=True)
     assert rr < 2e-5, rr
+
+
+_gold_gm = None
+
+
+def gold_gm():
+    """gm samples at n = 144, 192, 256 with p = 4 (tests/golden/make_gm_fullsize.py, oracle only)."""
+    global _gold_gm
+    if _gold_gm is None:
+        import json
+        import os
+        with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_gm_fullsize.json")) as fh:
+            _gold_gm = json.load(fh)
+    return _gold_gm
+
+
+@pytest.mark.parametrize("n,prec,tol", [(144, "c128", 1e-13), (144, "c64", 1e-6), (192, "c128", 1e-13),
+                                        (192, "c64", 1e-6), (256, "c128", 1e-13), (256, "c64", 1e-6)])
+def test_impulse_response_p4_fullsize(n, prec, tol):
+    # the p = 4 Proposition 2 kernel that the 256^3 workload and the n = 144 bead use: the response of G
+    # to a unit voxel at array index (0, 0, 0) is gm[d] at offset d = the output index; compared with
+    # the oracle's gm at fixed and seeded offsets, relative to max |gm|
+    g = gold_gm()
+    assert abs(g["k"] - K) < 1e-15 and g["p"] == 4
+    s = g["sizes"][str(n)]
+    _ctx.clear()
+    torch.cuda.empty_cache()
+    print(f"[ctx] n={n} prec={prec} p=4", flush=True)
+    c = api.Context(n, K, p=4, xg=float(n), prec=prec, device=DEV)
+    v = torch.zeros((1, n, n, n), dtype=cdt(prec), device=DEV)
+    v[0, 0, 0, 0] = 1.0
+    out = c.ls_apply_G(v)[0]
+    got = np.array([complex(out[tuple(d)].item()) for d in s["offsets"]])
+    ref = np.array(s["re"]) + 1j * np.array(s["im"])
+    e = np.max(np.abs(got - ref)) / s["max_abs"]
+    print(f"[gm p=4] n={n} {prec}: max |G delta - gm| / max |gm| = {e:.2e}", flush=True)
+    del c
+    assert e < tol, (n, prec, e)

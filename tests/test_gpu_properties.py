@@ -129,3 +129,36 @@ def test_G_converges_to_the_continuous_convolution():
         del c
     print(f"[theorem 1] bump, max relative error at n = 32, 64, 128: {errs}", flush=True)
     assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-7
+
+
+def test_G_converges_at_the_full_sizes_with_p4():
+    # the same closed-form reference at the sizes of the large workloads and the bead (n = 144, 192,
+    # 256, p = 4, complex128).  The error of Theorem 1 is not monotone in n, so each error is compared
+    # with the oracle's at the same point (tests/golden/oracle_bump_fullsize.json, written by
+    # tests/golden/make_bump_fullsize.py from the oracle alone): equal to 1e-12, and all below 3e-11,
+    # so the 8-coset kernel built at these sizes is the kernel Theorem 1 describes
+    from oracle import bump
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_bump_fullsize.json")))
+    L, kb, a, q = gold["L"], gold["kb"], gold["a"], gold["q"]
+    pts = [tuple(p[::-1]) for p in gold["points_zyx"]]
+    refs = [bump.conv_exact(float(np.sqrt(x * x + y * y + z * z)), kb, a, q) for (x, y, z) in pts]
+    for n in (144, 192, 256):
+        _ctx.clear()
+        torch.cuda.empty_cache()
+        h = L / n
+        print(f"[ctx] n={n} c128 p=4 (bump)", flush=True)
+        c = api.Context(n, kb * h, p=4, xg=float(n), prec="c128", device=DEV)
+        cc = (np.arange(n) - n // 2 + 1) * h
+        r = np.sqrt(cc[:, None, None] ** 2 + cc[None, :, None] ** 2 + cc[None, None, :] ** 2)
+        v = torch.from_numpy(bump.bump(r, a, q).astype(np.complex128)).to(DEV)
+        del r
+        Gv = (h * h) * c.ls_apply_G(v[None].contiguous())[0]
+        errs = []
+        for (x, y, z), ref in zip(pts, refs):
+            i = tuple(int(round(t / h)) + n // 2 - 1 for t in (z, y, x))
+            errs.append(abs(complex(Gv[i].item()) - ref) / abs(ref))
+        del c, v, Gv
+        print(f"[theorem 1] bump, n = {n} (p = 4): relative errors {errs}; oracle {gold['err'][str(n)]}", flush=True)
+        assert max(errs) < 3e-11
+        for e, eo in zip(errs, gold["err"][str(n)]):
+            assert abs(e - eo) <= 1e-12

@@ -257,3 +257,63 @@ def test_warm_start_at_128_c64():
     assert e < 1e-4
     _, iagain = c.ls_forward(f, d, tol=1e-5, u=uwarm.clone(), warm_start=True)
     assert all(i["status"] == 0 and i["iters"] == 0 for i in iagain)
+
+
+@pytest.mark.parametrize("n,radius,eta,eps", [(8, 3.0, 1.6, 0.5), (8, 3.0, 1.6, 0.999999), (16, 5.0, 1.6, 0.5)])
+def test_breakdown_restarts_follow_the_oracle(n, radius, eta, eps):
+    # the breakdown threshold of the restart test raised from the unit roundoff (ls_solve_opts.breakdown)
+    # so that the restart (rh = r, p = v = 0, rho_prev = alpha = omega = 1) fires several times;
+    # complex128 must take the oracle's restarts at the same iterations: same iteration and restart
+    # counts, solutions within 1e-10.  At 0.999999 every iteration after the first restarts.  (The
+    # cosines |<rh, r>| / (||rh|| ||r||) of these runs stay >= 8e-3 away from 1/2, far above rounding.)
+    f = workloads.sphere_potential(n, radius, eta)
+    c = ctx(n, "c128")
+    u, info = c.ls_forward(torch.from_numpy(f).to(DEV), [[0, 0, 1]], tol=1e-10, max_restarts=100, breakdown=eps)
+    b = incident.plane_wave(n, K, [0, 0, 1])
+    uo, io = solver.bicgstab(lambda v: ops.A_apply(ghat(n), f, v), b, 1e-10, max_restarts=100, eps=eps)
+    print(f"[breakdown {eps}] n={n}: GPU {info[0]['iters']} iterations, {info[0]['restarts']} restarts; "
+          f"oracle {io.iters}, {io.restarts}; rel {rel(u[0].cpu().numpy(), uo):.2e}", flush=True)
+    assert io.restarts > 0 and info[0]["status"] == 0
+    assert (info[0]["iters"], info[0]["restarts"]) == (io.iters, io.restarts)
+    assert rel(u[0].cpu().numpy(), uo) < 1e-10
+    if eps > 0.9:
+        assert info[0]["restarts"] == info[0]["iters"] - 1
+    with pytest.raises(RuntimeError):
+        c.ls_forward(torch.from_numpy(f).to(DEV), [[0, 0, 1]], tol=1e-10, breakdown=1.0)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_warm_start_with_zero_incident_field_returns_zero(prec):
+    # b = 0: the solution of A x = 0 is x = 0 whatever the initial guess (the oracle returns zeros);
+    # the warm start must not hand back the guess
+    n = 16
+    c = ctx(n, prec)
+    cd = torch.complex128 if prec == "c128" else torch.complex64
+    rd = torch.float64 if prec == "c128" else torch.float32
+    f = torch.from_numpy(workloads.sphere_potential(n, 5.0, 1.5)).to(DEV, rd)
+    uin = torch.zeros((2, n, n, n), dtype=cd, device=DEV)
+    uin[1] = torch.from_numpy(incident.plane_wave(n, K, [0, 0, 1])).to(DEV, cd)
+    x0 = torch.from_numpy(workloads.random_field(5, (2, n, n, n))).to(DEV, cd)
+    u, info = c.ls_forward_uin(f, uin, tol=1e-8 if prec == "c128" else 1e-5, u=x0.clone(), warm_start=True)
+    assert info[0]["status"] == 0 and info[0]["iters"] == 0
+    assert not torch.any(u[0] != 0)
+    assert info[1]["status"] == 0 and info[1]["iters"] > 0      # the other slot solves as usual
+
+
+@pytest.mark.parametrize("n,prec,Q,maxit", [(32, "c128", 3, 500), (32, "c64", 5, 500), (32, "c64", 5, 2),
+                                            (128, "c64", 60, 500)])
+def test_forward_farfield_equals_forward_then_farfield(n, prec, Q, maxit):
+    # the fused call reuses the x-spectrum of f . u from the solver's last true-residual check; the
+    # fields must equal those of ls_forward followed by ls_farfield bit for bit (also when the
+    # iteration cap stops the solves), at the benchmark's configuration too
+    c = ctx(n, prec)
+    rd = torch.float64 if prec == "c128" else torch.float32
+    f = torch.from_numpy(workloads.blob_potential(0, n, dn_max=0.05)).to(DEV, rd)
+    dirs = workloads.cone_dirs(Q, 45.0)
+    u1, info1 = c.ls_forward(f, dirs, tol=1e-5, maxit=maxit)
+    y1 = c.ls_farfield(f, u1)
+    u2, y2, info2 = c.ls_forward_farfield(f, dirs, tol=1e-5, maxit=maxit)
+    assert [i["status"] for i in info1] == [i["status"] for i in info2]
+    if maxit == 2:
+        assert all(i["status"] == 1 for i in info2)
+    assert torch.equal(u1, u2) and torch.equal(y1, y2)

@@ -36,7 +36,8 @@ class FakeCtx:
         if out is not None:
             out.copy_(r)
             r = out
-        return r, stats.reshape(-1).to(torch.float64)
+        st = stats.reshape(-1).to(torch.float64)
+        return r, st, (st[0::2] / (2 * st[1::2])).sum()
 
     def ls_farfield_adj(self, r, conj=False):
         return (r.conj() if conj else r).unsqueeze(1).expand(-1, n, -1, -1).contiguous()

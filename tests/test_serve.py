@@ -3,6 +3,7 @@ slots as they open, FIFO order, the two phases of gradient requests, capacity li
 accounting.  The fake engine finishes a job after a fixed number of iterations derived from its
 request, which is all the scheduler observes of a solve."""
 import numpy as np
+import pytest
 
 from paper_1910_13844_amd import serve
 
@@ -149,3 +150,95 @@ def test_concurrent_scheduler_completes_the_same_work():
     for r in trace:
         names = [e[0] for e in eng.log if len(e) >= 2 and e[1] == r.rid]
         assert names.count("ffwd") == 1 and names.count("fgrad") == (1 if r.kind == "grad" else 0)
+
+
+class BudgetFakeEngine(FakeEngine):
+    """FakeEngine whose requests hold device bytes (serve.request_bytes, complex64) from their first
+    admission to completion, charged to a serve.Ledger the way the GPU engine charges them."""
+
+    def __init__(self, capacity, budget):
+        super().__init__(capacity)
+        self.ledger = serve.Ledger(budget)
+        self.live = set()
+        self.max_live = 0
+
+    def reserve(self, req):
+        nbytes = serve.request_bytes(req.kind, req.n, req.Q, 8)
+        if nbytes > self.ledger.budget:
+            raise MemoryError(req.rid)
+        ok = self.ledger.try_charge(("req", req.rid), nbytes)
+        self.log.append(("reserve", req.rid, ok))
+        return ok
+
+    def prepare(self, req):
+        super().prepare(req)
+        self.live.add(req.rid)
+        self.max_live = max(self.max_live, len(self.live))
+
+    def _done(self, req):
+        self.live.discard(req.rid)
+        self.ledger.release(("req", req.rid))
+
+    def finish_forward(self, req):
+        super().finish_forward(req)
+        if req.kind == "forward":
+            self._done(req)
+
+    def finish_grad(self, req):
+        super().finish_grad(req)
+        self._done(req)
+
+
+def test_request_bytes_counts_every_request_owned_field():
+    n, Q, c = 64, 3, 8
+    N, M = n ** 3, n * n
+    assert serve.request_bytes("forward", n, Q, c) == Q * (N + M) * c                      # u, y
+    assert serve.request_bytes("grad", n, Q, c) == (Q * (3 * N + 2 * M) * c + 2 * Q * 8   # u w b, y r, stats
+                                                    + N * 4)                                # gradient
+
+
+@pytest.mark.parametrize("sched", ["single", "concurrent"])
+def test_admission_by_footprint_never_exceeds_the_budget(sched):
+    # a burst of requests (64^3 gradients, 2 illuminations: 13 MB each in complex64) into a pool of
+    # 8 slots and a budget that holds two of them: the ledger never passes the budget, at most two
+    # requests hold fields at once, the others wait (reserve refused) instead of allocating although
+    # slots are free, and all complete
+    per = serve.request_bytes("grad", 64, 2, 8)
+    trace = [serve.Request(i, "grad", 64, 2, 0.0, i, 40.0) for i in range(6)]
+    eng = (BudgetLockedFakeEngine if sched == "concurrent" else BudgetFakeEngine)(capacity=8, budget=2.5 * per)
+    cls = serve.ConcurrentScheduler if sched == "concurrent" else serve.Scheduler
+    res = cls(eng, iters_per_step=1, clock=eng.clock).run(trace, realtime=False)
+    assert res["requests"] == 6
+    assert eng.ledger.peak <= eng.ledger.budget and eng.ledger.used == 0
+    assert eng.max_live == 2
+    assert any(e[0] == "reserve" and not e[2] for e in eng.log)
+    # a refused request is admitted later, in arrival order
+    first = [e[1] for e in eng.log if e[0] == "prepare"]
+    assert first == sorted(first)
+
+
+def test_request_that_can_never_fit_is_an_error():
+    trace = [serve.Request(0, "grad", 64, 40, 0.0, 0, 40.0)]
+    eng = BudgetFakeEngine(capacity=4, budget=1e6)
+    with pytest.raises(MemoryError):
+        serve.Scheduler(eng, iters_per_step=1, clock=eng.clock).run(trace, realtime=False)
+
+
+def test_ledger_charges():
+    led = serve.Ledger(100)
+    led.charge(("pool", 1), 60)
+    assert not led.try_charge(("req", 1), 50) and led.used == 60
+    assert led.try_charge(("req", 2), 40) and led.used == 100 and led.peak == 100
+    with pytest.raises(MemoryError):
+        led.charge(("req", 3), 1)
+    assert led.release(("req", 2)) == 40 and led.used == 60 and led.held(("pool",)) == 60
+
+
+class BudgetLockedFakeEngine(BudgetFakeEngine, LockedFakeEngine):
+    """Thread-safe BudgetFakeEngine for the concurrent scheduler."""
+
+    def __init__(self, capacity, budget):
+        LockedFakeEngine.__init__(self, capacity)
+        self.ledger = serve.Ledger(budget)
+        self.live = set()
+        self.max_live = 0
