@@ -13,13 +13,14 @@ LIB_PATH = os.environ.get("LS_LIBRARY", os.path.join(HERE, "libls.so"))
 
 LS_C64 = 0
 LS_C128 = 1
+LS_SCRATCH_BYTES = 256 * 1024 * 1024   # fixed device scratch of ls_forward_farfield_noalloc
 LS_OP_FORWARD, LS_OP_FARFIELD, LS_OP_GRAD, LS_OP_APPLY, LS_OP_PROX, LS_OP_INCIDENT = 0, 1, 2, 3, 4, 5
 
 # every symbol declared in include/ls.h
 EXPORTS = [
     "ls_strerror", "ls_last_error", "ls_kernel_bytes", "ls_init_workspace_bytes", "ls_green_init",
     "ls_ctx_destroy", "ls_workspace_bytes", "ls_apply_G", "ls_apply_A", "ls_forward", "ls_forward_farfield",
-    "ls_farfield",
+    "ls_forward_farfield_noalloc", "ls_farfield",
     "ls_farfield_adj", "ls_vjp", "ls_grad", "ls_batch_bytes", "ls_batch_create", "ls_batch_admit",
     "ls_batch_step", "ls_batch_poll", "ls_batch_release", "ls_batch_destroy", "ls_profile_pass",
     "ls_residual", "ls_grad_accumulate", "ls_prox_tv", "ls_fbs_extrapolate", "ls_tv_value",
@@ -75,6 +76,7 @@ def load() -> C.CDLL:
         "ls_apply_A": (C.c_int, [vp, vp, vp, vp, i32, vp, sz, vp]),
         "ls_forward": (C.c_int, [vp, vp, i32, dp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
         "ls_forward_farfield": (C.c_int, [vp, vp, i32, dp, vp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),
+        "ls_forward_farfield_noalloc": (C.c_int, [vp, vp, i32, dp, vp, vp, P(SolveOpts), P(SolveInfo), vp]),
         "ls_farfield": (C.c_int, [vp, vp, vp, i32, vp, vp, sz, vp]),
         "ls_farfield_adj": (C.c_int, [vp, vp, i32, i32, vp, vp, sz, vp]),
         "ls_vjp": (C.c_int, [vp, vp, vp, i32, vp, vp, P(SolveOpts), P(SolveInfo), vp, sz, vp]),

@@ -172,6 +172,23 @@ class Context:
                 "ls_forward_farfield")
         return u, y, [i.as_dict() for i in info]
 
+    def ls_forward_farfield_noalloc(self, f: torch.Tensor, dirs, u: torch.Tensor, y: torch.Tensor, tol: float = 1e-5,
+                                    maxit: int = 500, max_restarts: int = 3, stream=None, warm_start: bool = False,
+                                    breakdown: float = 0.0) -> List[dict]:
+        """ls_forward_farfield into the caller's u [Q, n, n, n] and y [Q, n, n] with the library's fixed
+        device scratch (no workspace, nothing allocated on the device); returns the solve info."""
+        f = self._chk_f(f)
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        Q = d.shape[0]
+        self._chk_like(u, (Q, self.n, self.n, self.n), self.cdtype, "u")
+        self._chk_like(y, (Q, self.n, self.n), self.cdtype, "y")
+        info = (L.SolveInfo * Q)()
+        o = self._opts(tol, maxit, max_restarts, 1 if warm_start else 0, breakdown)
+        L.check(self.lib.ls_forward_farfield_noalloc(self.h, _ptr(f), Q, d.ctypes.data_as(C.POINTER(C.c_double)),
+                                                     _ptr(u), _ptr(y), C.byref(o), info, _stream(stream)),
+                "ls_forward_farfield_noalloc")
+        return [i.as_dict() for i in info]
+
     def ls_forward_uin(self, f: torch.Tensor, uin: torch.Tensor, tol: float = 1e-5, maxit: int = 500,
                        max_restarts: int = 3, u: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
                        stream=None, warm_start: bool = False, breakdown: float = 0.0) -> Tuple[torch.Tensor, List[dict]]:

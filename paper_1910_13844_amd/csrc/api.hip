@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -434,6 +435,41 @@ int ls_init_workspace_bytes(const ls_geom* g, size_t* bytes) {
   return LS_OK;
 }
 
+// Fixed device scratch of ls_forward_farfield_noalloc: one copy per device, loaded with the library's
+// code object and held until the process ends.  In host code `scratch` names a host-side stand-in,
+// not the device array: its device address comes from hipGetSymbolAddress, resolved once per device
+// with that device current (scratch_address) and used everywhere host code needs the array.
+static __device__ __align__(256) char scratch[LS_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on first use per device).
+int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_last_error = "scratch: device ordinal out of range";
+    return LS_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) {
+      g_last_error = "hipGetSymbolAddress(scratch) returned a null address";
+      return LS_ERR_HIP;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return LS_OK;
+}
+}  // namespace
+
 int ls_green_init(const ls_geom* g, void* kbuf, size_t kbuf_bytes, void* ws, size_t ws_bytes, void* stream,
                   ls_ctx** out) {
   int rc = geom_check(g);
@@ -447,6 +483,10 @@ int ls_green_init(const ls_geom* g, void* kbuf, size_t kbuf_bytes, void* ws, siz
   int dev = 0, clk = 0;
   HIPCHK(hipGetDevice(&dev));
   if (hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, dev) != hipSuccess) clk = 0;
+  {  // set-up of the fixed scratch on this device (the no-allocation entry point retries if this fails)
+    void* p = nullptr;
+    (void)scratch_address(&p);
+  }
   ls_ctx* c = new (std::nothrow) ls_ctx;
   if (!c) return LS_ERR_ARG;
   c->g = *g;
@@ -694,6 +734,21 @@ int ls_forward_farfield(const ls_ctx* c, const void* f, int32_t Q, const double*
                         const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   if (check_ctx(c) || !f || !dirs || !u || !y || !ws || Q < 1) return LS_ERR_ARG;
   return forward_common(c, f, Q, dirs, nullptr, u, y, opts, info, ws, ws_bytes, stream);
+}
+
+int ls_forward_farfield_noalloc(const ls_ctx* c, const void* f, int32_t Q, const double* dirs, void* u, void* y,
+                                const ls_solve_opts* opts, ls_solve_info* info, void* stream) {
+  if (check_ctx(c) || !f || !dirs || !u || !y || Q < 1) return LS_ERR_ARG;
+  if (ws_layout(c, 1, LS_OP_FORWARD).total > (size_t)LS_SCRATCH_BYTES) {
+    g_last_error = "ls_forward_farfield_noalloc: one illumination of this grid needs " +
+                   std::to_string(ws_layout(c, 1, LS_OP_FORWARD).total) + " bytes of scratch, more than the " +
+                   std::to_string((size_t)LS_SCRATCH_BYTES) + " bytes of the fixed device scratch";
+    return LS_ERR_WORKSPACE;
+  }
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  return forward_common(c, f, Q, dirs, nullptr, u, y, opts, info, ws, (size_t)LS_SCRATCH_BYTES, stream);
 }
 
 int ls_forward_uin(const ls_ctx* c, const void* f, int32_t Q, const void* uin, void* u, const ls_solve_opts* opts,
