@@ -393,4 +393,89 @@ __device__ __forceinline__ void fft_b2a(cplx<T> (&a)[Split<N>::E], cplx<T>* buf,
   SmallDFT<E, DIR, T>::run(a);
 }
 
+// R rows at once: the same four-step transforms for R independent rows of one lane group, each
+// row stored at stride 1 from rows[r] (its own scratch).  Interleaving the rows between the fences
+// gives the wavefront R independent chains to overlap LDS latency with.
+// rows_a2b: layout-A registers -> spectrum stored in bpos() order in each row.
+template <typename T, int N, int DIR, int R>
+__device__ __forceinline__ void rows_a2b(cplx<T> (&a)[R][Split<N>::E], cplx<T>* const (&rows)[R], int lane,
+                                         const cplx<T>* twl) {
+  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+#pragma unroll
+  for (int r = 0; r < R; ++r) SmallDFT<E, DIR, T>::run(a[r]);
+  if constexpr (L > 1) {
+#pragma unroll
+    for (int k1 = 1; k1 < E; ++k1) {
+      const cplx<T> w = twl_get<T, DIR>(twl, k1 * L + lane);
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r][k1] = a[r][k1] * w;
+    }
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) rows[r][tpos<N>(k1, lane)] = a[r][k1];
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+#pragma unroll
+        for (int m = 0; m < L; ++m) a[r][t * L + m] = rows[r][tpos<N>(lane * P + t, m)];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < P; ++t) SmallDFT<L, DIR, T>::run(&a[r][t * L]);
+  }
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int k2 = 0; k2 < L; ++k2) rows[r][bpos<N>(lane, t, k2)] = a[r][t * L + k2];
+  wave_sync();
+}
+
+// rows_b2a: spectrum in bpos() order in each row -> layout-A registers (the rows are scratch).
+template <typename T, int N, int DIR, int R>
+__device__ __forceinline__ void rows_b2a(cplx<T> (&a)[R][Split<N>::E], cplx<T>* const (&rows)[R], int lane,
+                                         const cplx<T>* twl) {
+  constexpr int L = Split<N>::L, E = Split<N>::E, P = E / L;
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+#pragma unroll
+      for (int k2 = 0; k2 < L; ++k2) a[r][t * L + k2] = rows[r][bpos<N>(lane, t, k2)];
+  if constexpr (L > 1) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < P; ++t) SmallDFT<L, DIR, T>::run(&a[r][t * L]);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+#pragma unroll
+        for (int m = 0; m < L; ++m) rows[r][tpos<N>(lane * P + t, m)] = a[r][t * L + m];
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) a[r][k1] = rows[r][tpos<N>(k1, lane)];
+#pragma unroll
+    for (int k1 = 1; k1 < E; ++k1) {
+      const cplx<T> w = twl_get<T, DIR>(twl, k1 * L + lane);
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r][k1] = a[r][k1] * w;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) SmallDFT<E, DIR, T>::run(a[r]);
+  wave_sync();
+}
+
 }  // namespace ls

@@ -931,6 +931,11 @@ struct ClassCfg {
   // z-convolution only; its row transforms elsewhere stay Stockham.
   static constexpr bool ZFOUR = (HasSplit<N>::value || N == 144) && !(sizeof(T) == 8 && (N == 96 || N == 144));
   static constexpr int PITCH = M + 1;
+  // fold and forward row DFTs straight from global memory, inverse row DFTs straight to it, with
+  // R rows per lane group (complex64 at 128 and 192: 2.46 against 3.01 ms per 60-slot launch at
+  // 128); the other sizes stage both through the slab (measured faster at 144 and 256, whose folds
+  // read three or four points per value; complex128 needs the registers for its longer folds)
+  static constexpr bool FUSED = sizeof(T) == 4 && (N == 128 || N == 192);
   static_assert(C == 2 || (HasSplit<M>::value && N % M == 0 && M % 16 == 0), "class slab shape");
 };
 
@@ -944,11 +949,71 @@ __device__ __forceinline__ void fill_twl_stride(cplx<T>* twl, const cplx<T>* tw,
   }
 }
 
+// Folded values of R rows (lane holds j = lane + L e of row zz[r]), read straight from the plane:
+// sum_m x[zz, j + m M] exp(-i pi c (j + m M) / n).  RC >= 0: four classes with two points per folded
+// value, class RC (rho = exp(-2 pi i RC / 4) is a power of -i, so x_0 + rho x_1 is a register
+// permutation, then one twiddle); RC < 0: any C.
+template <typename T, int N, int M, int F, int R, int RC>
+__device__ __forceinline__ void fold_rows(cplx<T> (&v)[R][Split<M>::E], const char* plane0, const int (&zz)[R],
+                                          const cplx<T>* tw, int c, int lane) {
+  constexpr int LM = Split<M>::L, EM = Split<M>::E;
+  auto x = [&](int r, int e, int m) {
+    return ldo<T>(plane0, (uint32_t)(zz[r] * N + lane + LM * e + m * M) * (uint32_t)sizeof(cplx<T>));
+  };
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+      const int j = lane + LM * e;
+      cplx<T> acc;
+      if constexpr (RC >= 0) {
+        const cplx<T> x0 = x(r, e, 0), x1 = x(r, e, 1);
+        acc = RC == 0 ? x0 + x1 : (RC == 1 ? x0 + mul_i<-1>(x1) : (RC == 2 ? x0 - x1 : x0 + mul_i<+1>(x1)));
+        if constexpr (RC != 0) acc = acc * tw[(RC * j) % (2 * N)];
+      } else {
+        acc = c == 0 ? x(r, e, 0) : x(r, e, 0) * tw[(c * j) % (2 * N)];
+#pragma unroll
+        for (int m = 1; m < F; ++m) acc = acc + x(r, e, m) * tw[(c * (j + m * M)) % (2 * N)];
+      }
+      v[r][e] = acc;
+    }
+}
+
+// Rows handled together by one lane group in the row phases of k_yzc (1 when the groups do not
+// divide the rows evenly, and in complex128, whose registers are taken by the z-convolution).
+template <typename T, int N>
+constexpr int yzc_rows() {
+  constexpr int M = ClassCfg<T, N>::M, G = ClassCfg<T, N>::NT / Split<M>::L;
+  return (N % G || sizeof(T) == 8) ? 1 : largest_divisor_upto(N / G, 2);
+}
+
+// Phase 1 of k_yzc for class value RC (or any class, RC < 0): fold, forward row DFT, spectrum to LDS.
+template <typename T, int N, int RC>
+__device__ __forceinline__ void yzc_rows_forward(cplx<T>* slab, const char* plane0, const cplx<T>* tw,
+                                                 const cplx<T>* twlM, int c, int tid) {
+  using CC = ClassCfg<T, N>;
+  constexpr int M = CC::M, F = N / M, PITCH = CC::PITCH;
+  constexpr int LM = Split<M>::L, EM = Split<M>::E, G = CC::NT / LM, R = yzc_rows<T, N>();
+  const int g = tid / LM, lane = tid - g * LM;
+#pragma unroll 1
+  for (int idx0 = g; idx0 < N; idx0 += G * R) {
+    cplx<T> v[R][EM];
+    int zz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) zz[r] = spreadL<N, LM>(idx0 + G * r);
+    fold_rows<T, N, M, F, R, RC>(v, plane0, zz, tw, c, lane);
+    cplx<T>* rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rows[r] = slab + spreadL<N, LM>(idx0 + G * r) * PITCH;
+    rows_a2b<T, M, -1, R>(v, rows, lane, twlM);
+  }
+}
+
 template <typename T, int N>
 __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k_yzc(PassArgs a) {
   using CC = ClassCfg<T, N>;
-  constexpr int C = CC::C, M = CC::M, F = N / M, NT = CC::NT, PITCH = CC::PITCH;
-  constexpr int LM = Split<M>::L;
+  constexpr int C = CC::C, M = CC::M, NT = CC::NT, PITCH = CC::PITCH;
+  constexpr int LM = Split<M>::L, EM = Split<M>::E;
   __shared__ cplx<T> slab[N * PITCH];
   __shared__ cplx<T> tw[2 * N];
   __shared__ cplx<T> twlM[M];
@@ -969,9 +1034,33 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
   const size_t soff = (size_t)kx * N * N;
   const int kxp = kx <= N ? kx : 2 * N - kx;
   const cplx<T>* K = (const cplx<T>*)a.kern + (size_t)kxp * (4 * N * N);
-  // fold, with the loads of a chunk issued together
-  {
+  if constexpr (CC::FUSED) {
+    for (int i = tid; i < 2 * N; i += NT) tw[i] = ld<T>(a.tw, i);
+    __syncthreads();
+    fill_twl_stride<T, M, C>(twlM, tw, tid, NT);
+    if constexpr (CC::ZFOUR) fill_twl<T, N>(twlN, tw, tid, NT);
+    __syncthreads();
+    // phase 1: each lane group folds its rows straight from global memory into registers (the
+    // y-DFT of the class is an M-point DFT of the folded row), transforms them and leaves the
+    // spectra in LDS
     const char* plane0 = (const char*)Sv + soff * sizeof(cplx<T>);
+    if constexpr (C == 4 && N / M == 2) {
+      // class value uniform over the block: one specialised loop per value
+      if (c == 0)
+        yzc_rows_forward<T, N, 0>(slab, plane0, tw, twlM, c, tid);
+      else if (c == 1)
+        yzc_rows_forward<T, N, 1>(slab, plane0, tw, twlM, c, tid);
+      else if (c == 2)
+        yzc_rows_forward<T, N, 2>(slab, plane0, tw, twlM, c, tid);
+      else
+        yzc_rows_forward<T, N, 3>(slab, plane0, tw, twlM, c, tid);
+    } else {
+      yzc_rows_forward<T, N, -1>(slab, plane0, tw, twlM, c, tid);
+    }
+  } else {
+    // fold through the slab, with the loads of a chunk issued together, then the row DFTs in LDS
+    const char* plane0 = (const char*)Sv + soff * sizeof(cplx<T>);
+    constexpr int F = N / M;
     constexpr int PER = N * M / NT;
     constexpr int CH0 = 32 / F < 8 ? 32 / F : 8;  // at most 32 loads in flight per thread
     constexpr int CH = largest_divisor_upto(PER, CH0);
@@ -989,32 +1078,17 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
           xv[k][m] = ldo<T>(plane0, (uint32_t)(zz * N + j + m * M) * (uint32_t)sizeof(cplx<T>));
       }
       if (k0 == 0) __syncthreads();  // tw visible
-      if constexpr (C == 4 && F == 2) {
-        // sum_m x_m exp(-i pi c (j + m M) / n) = exp(-i pi c j / n) (x_0 + rho x_1), rho =
-        // exp(-2 pi i c / 4) a power of -i: one loop per class value (the branch is uniform), so
-        // the multiplication by rho is a register permutation
-        if (c == 0)
-          fold4<T, N, CH, NT, PITCH, 0>(slab, xv, tw, tid, k0);
-        else if (c == 1)
-          fold4<T, N, CH, NT, PITCH, 1>(slab, xv, tw, tid, k0);
-        else if (c == 2)
-          fold4<T, N, CH, NT, PITCH, 2>(slab, xv, tw, tid, k0);
-        else
-          fold4<T, N, CH, NT, PITCH, 3>(slab, xv, tw, tid, k0);
-      } else {
-        foldg<T, N, M, F, CH, NT, PITCH>(slab, xv, tw, tid, k0, c);
-      }
+      foldg<T, N, M, F, CH, NT, PITCH>(slab, xv, tw, tid, k0, c);
     }
-  }
-  fill_twl_stride<T, M, C>(twlM, tw, tid, NT);
-  if constexpr (CC::ZFOUR) fill_twl<T, N>(twlN, tw, tid, NT);
-  __syncthreads();
-  {
+    fill_twl_stride<T, M, C>(twlM, tw, tid, NT);
+    if constexpr (CC::ZFOUR) fill_twl<T, N>(twlN, tw, tid, NT);
+    __syncthreads();
     constexpr int G = NT / LM;
     const int g = tid / LM, lane = tid - g * LM;
     for (int idx = g; idx < N; idx += G) row_fft<T, M, -1>(slab + spreadL<N, LM>(idx) * PITCH, lane, tw, twlM);
   }
   __syncthreads();
+  // phase 2: z-convolution of the M columns of the slab
   if constexpr (CC::ZFOUR) {
     constexpr int L = Split<N>::L;
     constexpr int G = NT / L;
@@ -1035,17 +1109,35 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
     }
   }
   __syncthreads();
-  {
+  void* Ov = d.vec[V_SPE];
+  const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
+  if constexpr (!CC::FUSED) {
     constexpr int G = NT / LM;
     const int g = tid / LM, lane = tid - g * LM;
     for (int idx = g; idx < N; idx += G) row_fft<T, M, +1>(slab + spreadL<N, LM>(idx) * PITCH, lane, tw, twlM);
-  }
-  __syncthreads();
-  void* Ov = d.vec[V_SPE];
-  const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
-  for (int i = tid; i < N * M; i += NT) {
-    const int zz = i / M, j = i - zz * M;
-    stv<T>(Ov, ooff + i, slab[zz * PITCH + j]);
+    __syncthreads();
+    for (int i = tid; i < N * M; i += NT) {
+      const int zz = i / M, j = i - zz * M;
+      stv<T>(Ov, ooff + i, slab[zz * PITCH + j]);
+    }
+  } else {
+    // phase 3: inverse row DFTs from LDS into registers, written straight to the class-major output
+    constexpr int G = NT / LM, R = yzc_rows<T, N>();
+    const int g = tid / LM, lane = tid - g * LM;
+#pragma unroll 1
+    for (int idx0 = g; idx0 < N; idx0 += G * R) {
+      cplx<T> v[R][EM];
+      cplx<T>* rows[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) rows[r] = slab + spreadL<N, LM>(idx0 + G * r) * PITCH;
+      rows_b2a<T, M, +1, R>(v, rows, lane, twlM);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int zz = spreadL<N, LM>(idx0 + G * r);
+#pragma unroll
+        for (int e = 0; e < EM; ++e) stv<T>(Ov, ooff + (size_t)zz * M + lane + LM * e, v[r][e]);
+      }
+    }
   }
 }
 
