@@ -52,8 +52,8 @@ def classes(n, c128):
 def pass_model(n, Q, c128):
     """Algorithmic bytes (and the plane pass's flops) per launch of the four solver passes.
 
-    Bytes in units of N*c per slot:
-      k_xfwd (p-update prologue): read r p v (3) + f (0.5), write p (1) + x-spectrum (2) = 6.5
+    Bytes in units of N*c per slot (f, shared by the slots, counted once per launch):
+      k_xfwd (p-update prologue): read r p v (3), write p (1) + x-spectrum (2) = 6, + f
       k_yz   read the x-spectrum (2), write the class-split (y,z) output (4) = 6, + kernel once
       k_xinv (v epilogue): read the class output (4) + p, rh (2), write v (1) = 7
       k_update: read x p s t rh (5), write x r (2) = 7
@@ -62,11 +62,12 @@ def pass_model(n, Q, c128):
     (z-convolution)] + 6 flops per kernel product."""
     c = 16 if c128 else 8
     Nc = n ** 3 * c
+    f_bytes = n ** 3 * c // 2
     ker_bytes = (n + 1) * 4 * n * n * c
     C = classes(n, c128)
     Mc = 2 * n // C
     yz_flops = Q * 2 * n * C * (2 * n * 5 * Mc * math.log2(Mc) + Mc * 4 * 5 * n * math.log2(n) + 2 * Mc * n * 6)
-    return {"k_xfwd": (0, Q * 6.5 * Nc, 2), "k_yz": (1, Q * 6 * Nc + ker_bytes, 2),
+    return {"k_xfwd": (0, Q * 6 * Nc + f_bytes, 2), "k_yz": (1, Q * 6 * Nc + ker_bytes, 2),
             "k_xinv": (2, Q * 7 * Nc, 2), "k_update": (3, Q * 7 * Nc, 1)}, yz_flops
 
 
@@ -239,7 +240,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="B", choices=["A", "B", "C"])
+    ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D"],
+                    help="headline workload; D prints only the gradient workload's object (for profiling)")
     ap.add_argument("--prof-reps", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true", help="headline workload only (no configs, no accuracy)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -256,6 +258,9 @@ def main() -> int:
 
     from paper_1910_13844_amd import workloads
 
+    if args.workload == "D":
+        print(json.dumps(config_D(args.steps, args.warmup)), flush=True)
+        return 0
     W = workloads.WORKLOADS[args.workload]
     n, Q = W.n, W.Q
     c128 = W.precision == "c128"
