@@ -1116,19 +1116,21 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
     }
   }
   __syncthreads();
-  void* Ov = d.vec[V_SPE];
-  const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
   if constexpr (!CC::FUSED) {
     constexpr int G = NT / LM;
     const int g = tid / LM, lane = tid - g * LM;
     for (int idx = g; idx < N; idx += G) row_fft<T, M, +1>(slab + spreadL<N, LM>(idx) * PITCH, lane, tw, twlM);
     __syncthreads();
+    void* Ov = d.vec[V_SPE];
+    const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
     for (int i = tid; i < N * M; i += NT) {
       const int zz = i / M, j = i - zz * M;
       stv<T>(Ov, ooff + i, slab[zz * PITCH + j]);
     }
   } else {
     // phase 3: inverse row DFTs from LDS into registers, written straight to the class-major output
+    void* Ov = d.vec[V_SPE];
+    const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
     constexpr int G = NT / LM, R = yzc_rows<T, N>();
     const int g = tid / LM, lane = tid - g * LM;
 #pragma unroll 1
