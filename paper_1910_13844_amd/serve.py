@@ -400,9 +400,12 @@ class GpuEngine:
         return self.ledger.try_charge(("req", req.rid), nbytes)
 
     def memory_report(self) -> dict:
+        """Ledger totals (what the loop charged: peak and the fixed part), and the allocator's view: the
+        bytes allocated once the inputs were preloaded (fixed part + inputs) and the peak while serving."""
         return {"budget_bytes": self.ledger.budget, "peak_bytes": self.ledger.peak,
                 "fixed_bytes": self.ledger.held(("ctx", "ws", "pool")),
-                "torch_max_allocated_bytes": int(self.torch.cuda.max_memory_allocated(self.device))}
+                "allocated_after_preload_bytes": getattr(self, "preloaded_bytes", None),
+                "allocated_peak_while_serving_bytes": int(self.torch.cuda.max_memory_allocated(self.device))}
 
     def preload(self, trace: Sequence[Request], workers: int = 8):
         """Generate every request's inputs before the trace starts (not part of the served work):
@@ -442,6 +445,10 @@ class GpuEngine:
             c._ws.clear()
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+        # device memory held before serving starts: the kernels, far-field workspaces and slot pools
+        # (charged to the ledger) and the preloaded request inputs (not charged)
+        self.preloaded_bytes = int(torch.cuda.memory_allocated(self.device))
+        torch.cuda.reset_peak_memory_stats(self.device)
 
     def prepare(self, req: Request):
         c = self._ctx(req.n)
