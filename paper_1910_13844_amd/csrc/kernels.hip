@@ -327,6 +327,12 @@ struct XInvCfg {
   static constexpr bool WIDE = sizeof(T) == 4 && 2 * XCfg<N>::TY * XCfg<N>::PITCH * (int)sizeof(cplx<T>) > 56 * 1024;
   static constexpr int NT = WIDE ? 512 : 256;
   static constexpr int WPE = WIDE ? 4 : 1;
+  // class sum by a C-point DFT over the classes: a tile holds TY / (C/2) consecutive j of every
+  // period y = j + k 2n/C, k < C/2, so each class value is loaded once and gives the C/2 rows that
+  // share it.  It pays for the wide complex64 tiles (n = 256, eight classes: 6 % less time than
+  // Horner's rule); at n = 128 the extra registers of the C values per output cost more than the
+  // repeated class loads (which L2 serves) save, in either precision.
+  static constexpr bool DFTSUM = WIDE;
   static constexpr int IT = (XCfg<N>::TY * N + NT - 1) / NT;
   static constexpr int IT2 = (2 * N * XCfg<N>::TY + NT - 1) / NT;
   // outputs per thread handled in one chunk of the class sum (three chunk-sized register sets)
@@ -369,10 +375,47 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
   const int z = zb * ZB + (rem - slot * ZB);
   if (!slot_active(a, slot)) return;
   const int blk = z * NYT + tr;
-  const int y0 = ((tr / FA) + (tr % FA) * TPP) * TY;
+  constexpr bool DS = XI::DFTSUM && (CL == 4 || CL == 8) && TY % (CL / 2) == 0 && CM / (2 * TY / CL) == NYT;
+  constexpr int KP = DS ? CL / 2 : 1;   // periods per tile (DFTSUM)
+  constexpr int TYJ = TY / KP;          // consecutive j per period (DFTSUM)
+  const int y0 = DS ? tr * TYJ : ((tr / FA) + (tr % FA) * TPP) * TY;
+  // global y of tile row yy: TY consecutive rows, or (DFTSUM) KP runs of TYJ rows, CM apart
+  auto yrow = [&](int yy) { return DS ? y0 + yy % TYJ + (yy / TYJ) * CM : y0 + yy; };
   const SlotDesc& d = a.desc[slot];
   for (int i = tid; i < 2 * N; i += NTX) tw[i] = ld<T>(a.tw, i);
-  {
+  if constexpr (DS) {
+    static_assert(TY % KP == 0 && CM % TYJ == 0 && CM / TYJ == NYT, "DFT class-sum tiles");
+    // thread -> (kx, jj); per kx and class one TYJ-long row piece of the class-major array
+    const void* spec = d.vec[a.spec];
+    const size_t cstride = (size_t)2 * N * a.nz * CM * sizeof(cplx<T>);
+    constexpr int PAIRS = 2 * N * TYJ;
+    constexpr int PT = PAIRS / NTX;       // pairs per thread
+    static_assert(PAIRS % NTX == 0, "pairs per thread");
+    cplx<T> v[PT][CL];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int pidx = tid + q * NTX;
+      const int kx = pidx / TYJ, jj = pidx - (pidx / TYJ) * TYJ;
+      const uint32_t off = (uint32_t)((kx * a.nz + z) * CM + y0 + jj) * (uint32_t)sizeof(cplx<T>);
+#pragma unroll
+      for (int c = 0; c < CL; ++c) v[q][c] = ldo<T>((const char*)spec + (size_t)c * cstride, off);
+    }
+    __syncthreads();  // tw visible
+    fill_twl_any<T, N>(twl, tw, tid, NTX);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int pidx = tid + q * NTX;
+      const int kx = pidx / TYJ, jj = pidx - (pidx / TYJ) * TYJ;
+      const int j = y0 + jj;
+      // z_c = exp(+i pi c j / n) Y_c, then Y(j + k CM) = sum_c z_c exp(+2 pi i c k / C), k < C/2
+#pragma unroll
+      for (int c = 1; c < CL; ++c) v[q][c] = mulc(v[q][c], tw[(c * j) % (2 * N)]);
+      SmallDFT<CL, +1, T>::run(v[q]);
+      cplx<T>* buf = (kx & 1) ? bufO : bufE;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) buf[(k * TYJ + jj) * PITCH + spec_pos<N>(kx >> 1)] = v[q][k];
+    }
+  } else {
     static_assert(CL == 1 || (CM % TY == 0 && CL % 2 == 0), "y tiles must stay inside one period");
     const void* spec = d.vec[a.spec];
     const int j0 = y0 % CM;
@@ -447,13 +490,12 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
     }
   }
   __syncthreads();
-  const size_t row0 = ((size_t)z * N + y0) * N;
   cplx<T> q0[IT], q1[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int i = tid + it * NTX;
     if (i < TY * N) {
-      const size_t idx = row0 + i;
+      const size_t idx = ((size_t)z * N + yrow(i / N)) * N + i % N;
       if constexpr (EPI == EPI_AXV) {
         q0[it] = ldn<T>(d.vec[V_P], idx);
         q1[it] = ldn<T>(d.vec[V_RH], idx);
@@ -476,7 +518,7 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
     if (i < TY * N) {
       const int yy = i / N;
       const int x = i - yy * N;
-      const size_t idx = row0 + i;
+      const size_t idx = ((size_t)z * N + yrow(yy)) * N + x;
       const cplx<T> g = bufE[yy * PITCH + x] + mulc(bufO[yy * PITCH + x], tw[x]);
       if constexpr (EPI == EPI_STORE) {
         stv<T>(d.vec[a.sel], idx, g);
@@ -490,19 +532,19 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
         dot_acc(a1, t, q0[it]);
         a2.re += (double)t.re * t.re + (double)t.im * t.im;
       } else if constexpr (EPI == EPI_R0) {
-        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, y0 + yy, x);
+        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, yrow(yy), x);
         stv<T>(d.vec[V_X], idx, b);
         stv<T>(d.vec[V_R], idx, g);
         stv<T>(d.vec[V_RH], idx, g);
         a0.re += (double)g.re * g.re + (double)g.im * g.im;
         a1.re += (double)b.re * b.re + (double)b.im * b.im;
       } else if constexpr (EPI == EPI_TRUE) {
-        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, y0 + yy, x);
+        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, yrow(yy), x);
         const cplx<T> r = (b - q1[it]) + g;
         stv<T>(d.vec[V_R], idx, r);
         a0.re += (double)r.re * r.re + (double)r.im * r.im;
       } else if constexpr (EPI == EPI_R0X) {
-        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, y0 + yy, x);
+        const cplx<T> b = d.vec[V_B] ? q0[it] : plane_wave<T>(d, N, z, yrow(yy), x);
         const cplx<T> r = (b - q1[it]) + g;
         stv<T>(d.vec[V_R], idx, r);
         stv<T>(d.vec[V_RH], idx, r);
