@@ -333,6 +333,14 @@ struct XInvCfg {
   // Horner's rule); at n = 128 the extra registers of the C values per output cost more than the
   // repeated class loads (which L2 serves) save, in either precision.
   static constexpr bool DFTSUM = WIDE;
+  // whether the class sum of CL classes takes the DFT form; the plane pass then writes the classes
+  // z-major, [c][z][kx][j], so that the rows one tile reads per class lie in one 2n CM block
+  // instead of 2n lines a whole kx plane apart (which share L2 sets and evict each other before
+  // the neighbouring tiles have read the rest of each line)
+  static constexpr bool dftsum(int CL) {
+    return DFTSUM && (CL == 4 || CL == 8) && XCfg<N>::TY % (CL / 2) == 0 &&
+           (2 * N / CL) % (2 * XCfg<N>::TY / CL) == 0 && (2 * N / CL) / (2 * XCfg<N>::TY / CL) == XCfg<N>::NYT;
+  }
   static constexpr int IT = (XCfg<N>::TY * N + NT - 1) / NT;
   static constexpr int IT2 = (2 * N * XCfg<N>::TY + NT - 1) / NT;
   // outputs per thread handled in one chunk of the class sum (three chunk-sized register sets)
@@ -375,7 +383,7 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
   const int z = zb * ZB + (rem - slot * ZB);
   if (!slot_active(a, slot)) return;
   const int blk = z * NYT + tr;
-  constexpr bool DS = XI::DFTSUM && (CL == 4 || CL == 8) && TY % (CL / 2) == 0 && CM / (2 * TY / CL) == NYT;
+  constexpr bool DS = XI::dftsum(CL);
   constexpr int KP = DS ? CL / 2 : 1;   // periods per tile (DFTSUM)
   constexpr int TYJ = TY / KP;          // consecutive j per period (DFTSUM)
   const int y0 = DS ? tr * TYJ : ((tr / FA) + (tr % FA) * TPP) * TY;
@@ -385,7 +393,7 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
   for (int i = tid; i < 2 * N; i += NTX) tw[i] = ld<T>(a.tw, i);
   if constexpr (DS) {
     static_assert(TY % KP == 0 && CM % TYJ == 0 && CM / TYJ == NYT, "DFT class-sum tiles");
-    // thread -> (kx, jj); per kx and class one TYJ-long row piece of the class-major array
+    // thread -> (kx, jj); per kx and class one TYJ-long row piece of the z-major class array
     const void* spec = d.vec[a.spec];
     const size_t cstride = (size_t)2 * N * a.nz * CM * sizeof(cplx<T>);
     constexpr int PAIRS = 2 * N * TYJ;
@@ -396,7 +404,7 @@ __global__ __launch_bounds__((XInvCfg<T, N>::NT), (XInvCfg<T, N>::WPE)) void k_x
     for (int q = 0; q < PT; ++q) {
       const int pidx = tid + q * NTX;
       const int kx = pidx / TYJ, jj = pidx - (pidx / TYJ) * TYJ;
-      const uint32_t off = (uint32_t)((kx * a.nz + z) * CM + y0 + jj) * (uint32_t)sizeof(cplx<T>);
+      const uint32_t off = (uint32_t)((z * 2 * N + kx) * CM + y0 + jj) * (uint32_t)sizeof(cplx<T>);
 #pragma unroll
       for (int c = 0; c < CL; ++c) v[q][c] = ldo<T>((const char*)spec + (size_t)c * cstride, off);
     }
@@ -928,10 +936,11 @@ __global__ __launch_bounds__(PlaneCfg<N>::NT) void k_ffT(PassArgs a) {
 // and the cropped inverse of that class is the M-point inverse DFT Y_c, periodic in y with
 // period M, times exp(+i pi c y / n).  One workgroup per (slot, kx, c) holds an n x M slab in LDS:
 // fold, forward row DFTs, z-convolution of its M columns, inverse row DFTs, and writes Y_c to the
-// class-major spectrum [c][kx][z][j]; k_xinv sums the classes.  C = 2 is the parity split of
-// k_yz3 (no fold).  Larger C keeps the slab small enough for several workgroups per CU, so the
-// global-memory phases of one workgroup overlap the transforms of another, and it lets grids
-// whose whole n x n plane exceeds LDS (n = 192, 256) run the same way.
+// class-major spectrum [c][kx][z][j] (or [c][z][kx][j], ClassCfg::ZMAJOR); k_xinv sums the
+// classes.  C = 2 is the parity split of k_yz3 (no fold).  Larger C keeps the slab small enough
+// for several workgroups per CU, so the global-memory phases of one workgroup overlap the
+// transforms of another, and it lets grids whose whole n x n plane exceeds LDS (n = 192, 256) run
+// the same way.
 // Fold of one chunk for four classes (M = n / 2, two points per folded value) and class RC.
 template <typename T, int N, int CH, int NT, int PITCH, int RC>
 __device__ __forceinline__ void fold4(cplx<T>* slab, const cplx<T> (&xv)[CH][2], const cplx<T>* tw, int tid, int k0) {
@@ -985,6 +994,8 @@ struct ClassCfg {
   // 128); the other sizes stage both through the slab (measured faster at 144 and 256, whose folds
   // read three or four points per value; complex128 needs the registers for its longer folds)
   static constexpr bool FUSED = sizeof(T) == 4 && (N == 128 || N == 192);
+  // class output [c][z][kx][j] (else [c][kx][z][j]): the layout k_xinv's DFT class sum reads
+  static constexpr bool ZMAJOR = XInvCfg<T, N>::dftsum(C);
   static_assert(C == 2 || (HasSplit<M>::value && N % M == 0 && M % 16 == 0), "class slab shape");
 };
 
@@ -1164,13 +1175,22 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
     for (int idx = g; idx < N; idx += G) row_fft<T, M, +1>(slab + spreadL<N, LM>(idx) * PITCH, lane, tw, twlM);
     __syncthreads();
     void* Ov = d.vec[V_SPE];
-    const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
-    for (int i = tid; i < N * M; i += NT) {
-      const int zz = i / M, j = i - zz * M;
-      stv<T>(Ov, ooff + i, slab[zz * PITCH + j]);
+    if constexpr (CC::ZMAJOR) {
+      const size_t ooff = (size_t)c * 2 * N * N * M + (size_t)kx * M;
+      for (int i = tid; i < N * M; i += NT) {
+        const int zz = i / M, j = i - zz * M;
+        stv<T>(Ov, ooff + (size_t)zz * (2 * N * M) + j, slab[zz * PITCH + j]);
+      }
+    } else {
+      const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
+      for (int i = tid; i < N * M; i += NT) {
+        const int zz = i / M, j = i - zz * M;
+        stv<T>(Ov, ooff + i, slab[zz * PITCH + j]);
+      }
     }
   } else {
     // phase 3: inverse row DFTs from LDS into registers, written straight to the class-major output
+    static_assert(!CC::ZMAJOR, "fused store writes [c][kx][z][j]");
     void* Ov = d.vec[V_SPE];
     const size_t ooff = ((size_t)c * 2 * N + kx) * N * M;
     constexpr int G = NT / LM, R = yzc_rows<T, N>();
