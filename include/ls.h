@@ -132,12 +132,15 @@ int ls_forward(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, 
 int ls_forward_farfield(const ls_ctx* ctx, const void* f, int32_t Q, const double* dirs, void* u, void* y,
                         const ls_solve_opts* opts, ls_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
-/* ls_forward_farfield for callers that cannot allocate device memory (code under stream capture,
- * serving loops that must not call the allocator): the same computation, its scratch taken from a
- * fixed device array of LS_SCRATCH_BYTES that the library holds on each device it runs on until the
- * process ends (no workspace argument; no allocation in the call).  The batch runs in groups of as
- * many illuminations as fit that array.  Every call on one device shares the array: calls that
- * overlap on a device (other threads or streams) race and must be serialised by the caller.
+/* ls_forward_farfield for callers that cannot allocate device memory (serving loops and harnesses
+ * that must not call the allocator): the same computation, its scratch taken from a fixed device
+ * array of LS_SCRATCH_BYTES that the library holds on each device it runs on until the process ends
+ * (no workspace argument; no allocation in the call).  Like ls_forward it waits on `stream` between
+ * groups of iterations to read the solver states, so it cannot be recorded under stream capture.
+ * The batch runs in groups of as many illuminations as fit that array.  Every call on one device
+ * shares the array, which keeps the last call's contents (each call writes every part it reads
+ * before reading it): calls that overlap on a device (other threads or streams) race and must be
+ * serialised by the caller.
  * Errors: LS_ERR_WORKSPACE when one illumination of the context's grid needs more scratch than
  * LS_SCRATCH_BYTES (for complex64 up to n = 128; complex128 up to n = 96); otherwise as
  * ls_forward_farfield. */
