@@ -1662,6 +1662,8 @@ static hipError_t xinv_t(const PassArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, 1>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a);
     return hipGetLastError();
   }
+  // the class output of the (y,z) pass covers whole volumes (its layout assumes n z-rows)
+  if (a.nz != N) return hipErrorInvalidValue;
   switch (a.mode) {
     case EPI_STORE: hipLaunchKernelGGL((k_xinv<T, N, EPI_STORE, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
     case EPI_AXV: hipLaunchKernelGGL((k_xinv<T, N, EPI_AXV, CL>), nb, dim3(XInvCfg<T, N>::NT), 0, s, a); break;
