@@ -341,21 +341,34 @@ def main() -> int:
     return 0
 
 
+def kernel_code_sha(text):
+    """First 16 hex digits of the sha256 of kernel source text with its comments, leading and
+    trailing blanks and empty lines removed: edits to comments leave it unchanged, edits to code
+    do not."""
+    import hashlib
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", line).strip() for line in text.splitlines())
+    return hashlib.sha256("\n".join(line for line in lines if line).encode()).hexdigest()[:16]
+
+
+def kernel_sources_text():
+    src = os.path.join(ROOT, "paper_1910_13844_amd", "csrc")
+    return "".join(open(os.path.join(src, name)).read() for name in ("kernels.hip", "fft.hpp"))
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or
-    None when that summary is missing or was taken from a different kernel source."""
-    import hashlib
+    None when that summary is missing or was taken from different kernel code."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
-    src = os.path.join(ROOT, "paper_1910_13844_amd", "csrc")
     try:
-        sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read() +
-                            open(os.path.join(src, "fft.hpp"), "rb").read()).hexdigest()[:16]
+        sha = kernel_code_sha(kernel_sources_text())
         vals = {}
         for line in open(path):
             if ":" in line and not line.startswith("|"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-        if vals.get("kernel_source_sha256_16") != sha:
+        if vals.get("kernel_code_sha256_16") != sha:
             return None
         return float(vals[f"traffic_bytes_per_launch {kernel}"])
     except (OSError, KeyError, ValueError):

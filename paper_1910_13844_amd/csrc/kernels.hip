@@ -9,8 +9,10 @@
 //
 //   k_xfwd  [z][y][x] field -> x-spectrum [kx (2n)][z][y]           (prologue fuses f . x and
 //                                                                      the Krylov vector updates)
-//   k_yz    per (slot, kx) plane: y-DFT, z-convolution with ghat_m, inverse y-DFT, all in LDS
-//   k_xinv  [kx][z][y] -> cropped inverse x-DFT -> [z][y][x]          (epilogue fuses x - G(...)
+//   k_yzc   per (slot, kx, ky class): padded y-DFT of one class of C (ky = c mod C) as a
+//   k_yz3   2n/C-point DFT of the folded row, z-convolution with ghat_m, inverse, written
+//           class-major [c][kx][z][j] (k_yz3: C = 2, the parity split)
+//   k_xinv  class sum, cropped inverse x-DFT -> [z][y][x]              (epilogue fuses x - G(...)
 //                                                                      and FP64 partial dots)
 //
 // The far field (eq. (lipp2), P = I) reuses k_xfwd/k_xinv with k_ff / k_ffT in between.
