@@ -5,8 +5,9 @@ One step = ls_forward_farfield: BiCGSTAB to tol 1e-5 for all 60 plane waves on a
 (blob phantom seed 0, complex64 fields with FP64 reductions) and the far field of every solution
 (128 x 128 detector per illumination).  Inputs are resident in HBM before the timed region; the one-time Green-kernel
 build is timed separately.  Prints one JSON line whose headline is that workload; the same line
-carries the 256^3 x 60 forward workload and the 128^3 x 40-view gradient workload as
-sub-objects (`configs`), the accuracy of the timed batch against the complex128 path, and the
+carries the 256^3 x 60 forward workload, the 128^3 x 40-view gradient workload and a 100-request
+serving trace (continuous batching against one illumination at a time) as sub-objects
+(`configs`), the accuracy of the timed batch against the complex128 path, and the
 FP64 oracle timed on the host (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload B] [--no-extras] [--no-cpu-baseline]
@@ -235,6 +236,25 @@ def config_D(steps, warmup, dev="cuda:0"):
     return out
 
 
+def config_E(requests=100):
+    """Serving: a seeded Poisson trace of forward and gradient requests over grid sizes 64-192
+    (1-60 illuminations each, 20 requests/s), served with continuous batching and admission by
+    device-memory footprint, and the same requests one illumination at a time."""
+    from paper_1910_13844_amd import serve
+    res = serve.benchmark(requests=requests, baseline=True, progress=0)
+    cont, alone = res["continuous"], res["one_at_a_time"]
+    out = {"workload": f"serve_trace{requests}_c64", "requests": requests,
+           "value": round(cont["solves_per_s"], 2), "unit": "solves/s",
+           "p50_ms": round(cont["p50_ms"], 1), "p99_ms": round(cont["p99_ms"], 1),
+           "one_at_a_time": {"value": round(alone["solves_per_s"], 2), "p50_ms": round(alone["p50_ms"], 1),
+                             "p99_ms": round(alone["p99_ms"], 1)},
+           "speedup": round(cont["solves_per_s"] / alone["solves_per_s"], 3),
+           "results_equal_alone_vs_mix_max_rel": res["alone_vs_mix_max_rel"],
+           "memory": cont["memory"], "trace": res["config"]}
+    release()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,7 +354,7 @@ def main() -> int:
     f_np = W.potential()
     release(r)
     if not args.no_extras and args.workload == "B":
-        out["configs"] = {"C": config_C(2, 1, 2), "D": config_D(5, 1)}
+        out["configs"] = {"C": config_C(2, 1, 2), "D": config_D(5, 1), "E": config_E()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["oracle_check"] = cpu_baseline(W, f_np, out["solve"], u0, y0)
     print(json.dumps(out), flush=True)

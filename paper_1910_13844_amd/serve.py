@@ -501,7 +501,7 @@ class GpuEngine:
         self._done(req)
 
 
-def one_at_a_time(engine_factory, trace: Sequence[Request]) -> dict:
+def one_at_a_time(engine_factory, trace: Sequence[Request], progress: int = 50) -> dict:
     """Baseline: requests served in arrival order, each illumination solved alone (Q = 1 calls)."""
     import torch
 
@@ -537,7 +537,7 @@ def one_at_a_time(engine_factory, trace: Sequence[Request]) -> dict:
             e.finish_forward(req)
         req.done_time = time.perf_counter() - t0
         done.append(req)
-        if len(done) % 50 == 0:
+        if progress and len(done) % progress == 0:
             print(f"[serve] one-at-a-time: {len(done)} requests done at {req.done_time:.1f} s", file=sys.stderr,
                   flush=True)
     torch.cuda.synchronize()
@@ -558,6 +558,43 @@ def _max_rel_diff(a: Sequence[Request], b: Sequence[Request]) -> float:
     return worst
 
 
+def benchmark(requests: int = 400, rate: float = 20.0, grids: Sequence[int] = (64, 96, 128, 192), qmax: int = 60,
+              budget_gb: float = 120.0, baseline: bool = False, single_thread: bool = False,
+              progress: int = 50) -> dict:
+    """Serves a seeded Poisson trace with continuous batching on the GPU and, with `baseline`, the
+    same requests one illumination at a time; returns the throughput and latency summaries, the
+    memory report and the largest difference between the two runs' results."""
+    import torch
+
+    grids = list(grids)
+    mk = lambda: poisson_trace(requests, rate, grids, qmax)  # noqa: E731
+    inputs: dict = {}
+    eng = GpuEngine(hbm_budget_gb=budget_gb, inputs=inputs)
+    trace = mk()
+    t = time.perf_counter()
+    eng.preload(trace)
+    print(f"[serve] inputs for {len(trace)} requests ready in {time.perf_counter() - t:.1f} s", file=sys.stderr,
+          flush=True)
+    sched = (Scheduler if single_thread else ConcurrentScheduler)(eng, progress=progress)
+    res = {"continuous": sched.run(trace)}
+    torch.cuda.synchronize()
+    res["continuous"]["memory"] = eng.memory_report()
+    print(f"[serve] continuous: {res['continuous']}", file=sys.stderr, flush=True)
+    del sched, eng
+    torch.cuda.empty_cache()
+    if baseline:
+        trace_b = mk()
+        res["one_at_a_time"] = one_at_a_time(lambda: GpuEngine(hbm_budget_gb=budget_gb, inputs=inputs), trace_b,
+                                             progress=progress)
+        res["alone_vs_mix_max_rel"] = _max_rel_diff(trace, trace_b)
+        torch.cuda.empty_cache()
+    nsolve = sum(r.Q * (2 if r.kind == "grad" else 1) for r in trace)
+    res["config"] = {"requests": requests, "rate": rate, "grids": grids, "qmax": qmax,
+                     "scheduler": "single thread" if single_thread else "one thread and stream per pool",
+                     "solves_in_trace": nsolve, "trace_seconds": max(r.arrival for r in trace)}
+    return res
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=400)
@@ -569,32 +606,8 @@ def main(argv=None) -> int:
     ap.add_argument("--single-thread", action="store_true",
                     help="step the slot pools one after the other from one host thread")
     args = ap.parse_args(argv)
-    import torch
-
-    grids = [int(g) for g in args.grids.split(",")]
-    mk = lambda: poisson_trace(args.requests, args.rate, grids, args.qmax)  # noqa: E731
-    inputs: dict = {}
-    eng = GpuEngine(hbm_budget_gb=args.budget_gb, inputs=inputs)
-    trace = mk()
-    t = time.perf_counter()
-    eng.preload(trace)
-    print(f"[serve] inputs for {len(trace)} requests ready in {time.perf_counter() - t:.1f} s", file=sys.stderr,
-          flush=True)
-    sched = (Scheduler if args.single_thread else ConcurrentScheduler)(eng, progress=50)
-    res = {"continuous": sched.run(trace)}
-    torch.cuda.synchronize()
-    res["continuous"]["memory"] = eng.memory_report()
-    print(f"[serve] continuous: {res['continuous']}", file=sys.stderr, flush=True)
-    if args.baseline:
-        del sched, eng
-        torch.cuda.empty_cache()
-        trace_b = mk()
-        res["one_at_a_time"] = one_at_a_time(lambda: GpuEngine(hbm_budget_gb=args.budget_gb, inputs=inputs), trace_b)
-        res["alone_vs_mix_max_rel"] = _max_rel_diff(trace, trace_b)
-    nsolve = sum(r.Q * (2 if r.kind == "grad" else 1) for r in trace)
-    res["config"] = {"requests": args.requests, "rate": args.rate, "grids": grids, "qmax": args.qmax,
-                     "scheduler": "single thread" if args.single_thread else "one thread and stream per pool",
-                     "solves_in_trace": nsolve, "trace_seconds": max(r.arrival for r in trace)}
+    res = benchmark(args.requests, args.rate, [int(g) for g in args.grids.split(",")], args.qmax, args.budget_gb,
+                    args.baseline, args.single_thread)
     print(json.dumps(res), flush=True)
     return 0
 
