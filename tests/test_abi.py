@@ -67,6 +67,9 @@ def test_null_context_rejected(lib):
     b = C.c_size_t()
     assert lib.ls_workspace_bytes(None, 4, 0, C.byref(b)) == -1
     assert lib.ls_forward(None, None, 1, None, None, None, None, None, 0, None) == -1
+    assert lib.ls_forward_farfield(None, None, 1, None, None, None, None, None, None, 0, None) == -1
+    assert lib.ls_forward_farfield_noalloc(None, None, 1, None, None, None, None, None, None) == -1
+    assert lib.ls_residual(None, None, None, 1, 0, None, None, None, None) == -1
     assert lib.ls_strerror(-2).decode().startswith("workspace")
 
 
