@@ -1339,8 +1339,8 @@ __global__ __launch_bounds__(256) void k_update(PassArgs a) {
   constexpr int TY = X::TY, NYT = X::NYT, IT = X::IT;
   __shared__ double red[4 * 4];
   const int tid = threadIdx.x;
-  // XCD-aware slot-major order from n = 192 up (measured at 256^3: 9.42 against 9.83 ms; at 96
-  // and 144 launch order is as fast or faster)
+  // XCD-aware slot-major order from n = 192 up (measured at 256^3: 9.42 against 9.83 ms; at 96,
+  // 128 and 144 launch order is as fast or faster: complex64 at 128, 1.20 against 1.26 ms)
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   const int lin = (N >= 192 && nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
