@@ -1098,12 +1098,15 @@ __global__ __launch_bounds__((ClassCfg<T, N>::NT), (ClassCfg<T, N>::WPE)) void k
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   // consecutive blocks on one XCD: the C classes of one (kx, slot) plane (the plane is read once
-  // from HBM, then from L2), and all slots of one kx (the kernel plane stays in L2)
+  // from HBM, then from L2), all slots of one kx (the kernel plane stays in L2), and kx in the
+  // order 0, 1, 2n-1, 2, 2n-2, ..., n-1, n+1, n, so that kx and 2n - kx, which share a kernel
+  // plane, follow each other (256^3: 0.46 GB less read per launch)
   const int lin = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
   const int c = lin % C;
   const int ks = lin / C;
-  const int kx = ks / a.nslots;
-  const int slot = ks - kx * a.nslots;
+  const int sx = ks / a.nslots;
+  const int slot = ks - sx * a.nslots;
+  const int kx = sx == 0 ? 0 : (sx == 2 * N - 1 ? N : ((sx & 1) ? (sx + 1) / 2 : 2 * N - sx / 2));
   if (!slot_active(a, slot)) return;
   const int tid = threadIdx.x;
   const SlotDesc& d = a.desc[slot];
