@@ -47,7 +47,7 @@ def rel(a, b):
 def classes(n, c128):
     """ky classes of the (y,z) plane pass (ClassCfg in kernels.hip)."""
     return {True: {8: 2, 16: 2, 32: 2, 64: 2, 96: 6, 128: 8, 144: 18, 192: 12, 256: 16},
-            False: {8: 2, 16: 2, 32: 2, 64: 2, 96: 2, 128: 4, 144: 6, 192: 6, 256: 8}}[c128][n]
+            False: {8: 2, 16: 2, 32: 2, 64: 4, 96: 4, 128: 4, 144: 6, 192: 6, 256: 8}}[c128][n]
 
 
 def pass_model(n, Q, c128):

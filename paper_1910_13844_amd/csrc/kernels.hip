@@ -990,9 +990,11 @@ __device__ __forceinline__ void foldg(cplx<T>* slab, const cplx<T> (&xv)[CH][F],
 
 template <typename T, int N>
 struct ClassCfg {
-  // number of classes; 2 = k_yz3
+  // number of classes; 2 = k_yz3 (complex64 at 64 and 96: four classes, fused, take the plane pass
+  // from 0.294 to 0.243 and from 2.14 to 1.67 ms per 60-slot launch against the whole plane, for
+  // 0.013 and 0.06 ms more in the x-inverse's class sum; six classes at 96: 1.99 ms, 0.13 ms more)
   static constexpr int C = N == 144 ? (sizeof(T) == 4 ? 6 : 18)
-                          : sizeof(T) == 4 ? (N <= 96 ? 2 : (N == 128 ? 4 : (N == 192 ? 6 : 8)))
+                          : sizeof(T) == 4 ? (N <= 32 ? 2 : (N <= 128 ? 4 : (N == 192 ? 6 : 8)))
                                            : (N <= 64 ? 2 : (N == 96 ? 6 : (N == 128 ? 8 : (N == 192 ? 12 : 16))));
   static constexpr int M = 2 * N / C;
   // complex64 from 192 up: one 100-140 KB slab per CU, worked on by 8 waves (fewer classes make
@@ -1007,10 +1009,11 @@ struct ClassCfg {
   static constexpr bool ZFOUR = (HasSplit<N>::value || N == 144) && !(sizeof(T) == 8 && (N == 96 || N == 144));
   static constexpr int PITCH = M + 1;
   // fold and forward row DFTs straight from global memory, inverse row DFTs straight to it, with
-  // R rows per lane group (complex64 at 128 and 192: 2.46 against 3.01 ms per 60-slot launch at
-  // 128); the other sizes stage both through the slab (measured faster at 144 and 256, whose folds
-  // read three or four points per value; complex128 needs the registers for its longer folds)
-  static constexpr bool FUSED = sizeof(T) == 4 && (N == 128 || N == 192);
+  // R rows per lane group (complex64 at 64, 96, 128 and 192: 2.46 against 3.01 ms per 60-slot
+  // launch at 128, 1.67 against 1.95 at 96); the other sizes stage both through the slab (measured
+  // faster at 144 and 256, whose folds read three or four points per value; complex128 needs the
+  // registers for its longer folds)
+  static constexpr bool FUSED = sizeof(T) == 4 && (N == 64 || N == 96 || N == 128 || N == 192);
   // class output [c][z][kx][j] (else [c][kx][z][j]): the layout k_xinv's DFT class sum reads
   static constexpr bool ZMAJOR = XInvCfg<T, N>::dftsum(C);
   static_assert(C == 2 || (HasSplit<M>::value && N % M == 0 && M % 16 == 0), "class slab shape");
