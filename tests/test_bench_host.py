@@ -19,3 +19,11 @@ def test_kernel_code_sha_ignores_comments_only():
 def test_kernel_code_sha_of_the_sources():
     sha = bench.kernel_code_sha(bench.kernel_sources_text())
     assert len(sha) == 16 and int(sha, 16) >= 0
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    import subprocess
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert p.returncode != 0
+    assert "one GPU" in (p.stdout + p.stderr)
