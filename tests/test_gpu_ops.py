@@ -56,7 +56,7 @@ def test_apply_G(n, prec, tol):
         assert rel(out[q], ref) < tol, (n, prec, q, rel(out[q], ref))
 
 
-@pytest.mark.parametrize("n,prec,tol", [(16, "c128", 1e-12), (32, "c64", 2e-6)])
+@pytest.mark.parametrize("n,prec,tol", [(16, "c128", 1e-12), (32, "c64", 2e-6), (64, "c64", 2e-6), (96, "c64", 2e-6)])
 def test_apply_A(n, prec, tol):
     v = workloads.random_field(3, (1, n, n, n))
     f = workloads.blob_potential(1, n, dn_max=0.05)

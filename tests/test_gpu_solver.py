@@ -99,7 +99,7 @@ def test_cone_batch_c128():
         assert abs(info[q]["iters"] - io10.iters) <= max(2, io10.iters // 10)
 
 
-@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("n", [32, 64, 96])
 def test_c64_solution_within_1e4_of_tight_oracle(n):
     f = workloads.blob_potential(0, n, dn_max=0.05)
     dirs = workloads.cone_dirs(4, 45.0)
