@@ -154,3 +154,30 @@ def test_impulse_response_p4_fullsize(n, prec, tol):
     print(f"[gm p=4] n={n} {prec}: max |G delta - gm| / max |gm| = {e:.2e}", flush=True)
     del c
     assert e < tol, (n, prec, e)
+
+
+def test_c64_solve_at_192_matches_the_complex128_path():
+    # The serving trace's dominant grid, at the workloads' p = 4: complex64 solves and far fields
+    # (tol 1e-5) within the 1e-4 target of the complex128 path solved to 1e-10, which is checked
+    # against the oracle at 192 (G and the far field above, the p = 4 kernel's values in
+    # test_impulse_response_p4_fullsize).
+    _ctx.clear()
+    torch.cuda.empty_cache()
+    n = 192
+    f = workloads.blob_potential(0, n, dn_max=0.05)
+    dirs = workloads.cone_dirs(2, 45.0)
+    out = {}
+    for prec, tol in (("c128", 1e-10), ("c64", 1e-5)):
+        print(f"[solve192] {prec} tol {tol:g}", flush=True)
+        c = api.Context(n, K, p=4, xg=float(n), prec=prec, device=DEV)
+        rd = torch.float64 if prec == "c128" else torch.float32
+        u, y, info = c.ls_forward_farfield(torch.from_numpy(f).to(DEV, rd), dirs, tol=tol)
+        assert all(i["status"] == 0 for i in info), info
+        out[prec] = (u.cpu().numpy().astype(np.complex128), y.cpu().numpy().astype(np.complex128))
+        del c, u, y
+        torch.cuda.empty_cache()
+    for q in range(len(dirs)):
+        eu = rel(out["c64"][0][q], out["c128"][0][q])
+        ey = rel(out["c64"][1][q], out["c128"][1][q])
+        print(f"[solve192] q={q} u {eu:.2e} y {ey:.2e}", flush=True)
+        assert eu < 1e-4 and ey < 1e-4, (q, eu, ey)
